@@ -1,0 +1,187 @@
+/*
+ * sp2.h - C ABI of the SP2 density-matrix purification library (gfx950).
+ *
+ * The library computes the density matrix D of a symmetric matrix F with the
+ * second-order spectral projection (SP2) recursion and the parameterless
+ * stopping criterion of Kruchinina, Rudberg and Rubensson (2015), Alg. 2:
+ *
+ *   X_0  = (lambda_max I - F) / (lambda_max - lambda_min)        (Alg. 2)
+ *   X_i  = X~_{i-1}^2           if the trace test picks x^2      (p_i = 1)
+ *        = 2 X~_{i-1} - X~_{i-1}^2   otherwise                  (p_i = 0)
+ *   X~_i = X_i + E_i,  E_i = removal of entries with |x| < tau (sec. 5)
+ *   stop at step k >= 2 when p_k != p_{k-1} and
+ *        log(v_k / C) / log(v_{k-2}) < 1.8,  C = (71 + 17 sqrt 17)/32,
+ *   where v_k = ||X~_k - X~_k^2||_F (sec. 2, eq. eq:frobnorm) and the test
+ *   is evaluated only when 0 < v_{k-2} < 1.
+ *
+ * Readings of the paper that this interface fixes:
+ *   - n (n_iter) is the 0-based index of the returned iterate X~_n; n + 1
+ *     matrix squares were computed (the paper's printed iteration counts
+ *     equal n + 1).
+ *   - The default polynomial choice takes x^2 iff the trace it produces is
+ *     nearer to n_occ than the trace of 2x - x^2 (ties take 2x - x^2). This
+ *     equals Alg. 2's "Tr X > n_occ" whenever Tr X^2 <= Tr X, i.e. for every
+ *     spectrum inside [0,1]; the literal rule is SP2_BRANCH_LITERAL.
+ *   - n_occ == 0 returns D = 0 and n_occ == n returns D = I, both with n = 0.
+ *   - v_k == 0 exactly stops with n = k.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an sp2_status; nothing throws across the ABI.
+ *   - Pointers named *_dev are device pointers on the context's device;
+ *     every other pointer is host memory. The caller owns all memory it
+ *     passes; the context owns every workspace it allocates.
+ *   - Matrices are dense, row-major, with a leading dimension (elements
+ *     between the starts of consecutive rows) >= n. F must be symmetric;
+ *     only the upper triangle of the iterates is computed and mirrored, so
+ *     an asymmetric F is treated as given and not symmetrised.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Work is ordered on the context's HIP stream.
+ */
+#ifndef SP2_H
+#define SP2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Largest number of squares one run may compute. */
+#define SP2_MAX_ITER_LIMIT 200
+
+typedef struct sp2_ctx_s* sp2_ctx;
+
+typedef enum {
+  SP2_OK = 0,             /* success; for sp2_run: the stop criterion fired */
+  SP2_INVALID_ARG = 1,    /* an argument failed validation; nothing was run */
+  SP2_OUT_OF_MEMORY = 2,  /* a device or pinned-host allocation failed */
+  SP2_HIP_ERROR = 3,      /* a HIP runtime call failed; see sp2_last_error */
+  SP2_NOT_CONVERGED = 4,  /* max_iter squares computed, the stop never fired */
+  SP2_DIVERGED = 5,       /* non-finite error or trace, or Tr X^2 > Tr X + n:
+                             the bounds do not enclose the spectrum or F has
+                             non-finite entries */
+  SP2_BAD_STATE = 6       /* call out of order (e.g. sp2_run before init) */
+} sp2_status;
+
+/* Precision of the matrix squares and of the stored iterates. The affine
+ * start X_0 is always formed in FP64 from the FP64 input and then rounded to
+ * the storage precision; traces, the idempotency error and the stop test are
+ * always accumulated and evaluated in FP64. */
+typedef enum {
+  SP2_FP64 = 0,    /* FP64 iterates, FP64 MFMA squares */
+  SP2_FP32 = 1,    /* FP32 iterates, FP32 MFMA squares */
+  SP2_BF16X3 = 2   /* FP32 iterates; each square as H H + H L + L H with
+                      H = bf16(X), L = bf16(X - H) (round to nearest even),
+                      BF16 MFMA products accumulated in FP32 */
+} sp2_precision;
+
+typedef enum {
+  SP2_BRANCH_NEAREST = 0,  /* trace-nearest choice (default, see above) */
+  SP2_BRANCH_LITERAL = 1   /* Alg. 2 as printed: x^2 iff Tr X > n_occ */
+} sp2_branch;
+
+typedef struct {
+  int32_t precision;  /* sp2_precision */
+  int32_t branch;     /* sp2_branch */
+  double trunc_tau;   /* element-magnitude truncation threshold, 0 = off;
+                         entries with |x| < tau are set to zero in X_0 and
+                         after every polynomial step (sec. 5) */
+  int32_t max_iter;   /* at most this many squares; 0 selects 100; must be
+                         <= SP2_MAX_ITER_LIMIT */
+  int32_t tile;       /* macro-tile edge of the square kernel; 0 lets the
+                         library choose; otherwise one of the sizes the
+                         library reports through sp2_tile_supported */
+  int32_t kernel_timing; /* nonzero: bracket every square launch with a pair
+                            of HIP timing events (read back through
+                            sp2_get_kernel_times); adds a few microseconds
+                            per step */
+} sp2_options;
+
+/* Fills *opt with the defaults: SP2_FP64, SP2_BRANCH_NEAREST, no truncation,
+ * max_iter 100, tile 0, no kernel timing. */
+void sp2_default_options(sp2_options* opt);
+
+/* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the default stream) that every later call orders its work on.
+ * *out receives the handle. Errors: SP2_INVALID_ARG (out NULL, bad device),
+ * SP2_HIP_ERROR. */
+sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream);
+
+/* Releases every workspace of the context (after synchronising its stream)
+ * and the handle itself. NULL is accepted and ignored. */
+sp2_status sp2_destroy(sp2_ctx ctx);
+
+/* Prepares a dense run (Alg. 2 input: F, lambda_min, lambda_max, n_occ).
+ * F_dev: n x n FP64, row-major, leading dimension ldf >= n, symmetric.
+ * lambda_min <= smallest and lambda_max >= largest eigenvalue of F
+ * (sec. 3, bounds of the extremal eigenvalues); lambda_max > lambda_min.
+ * 0 <= n_occ <= n. opt may be NULL (defaults). Allocates the context's
+ * workspaces (two iterate buffers padded to the tile size, FP64 partial sums,
+ * the history) on first use or when n grows; reads nothing from F yet: F
+ * must stay valid until sp2_run returns.
+ * Errors: SP2_INVALID_ARG, SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. */
+sp2_status sp2_init_dense(sp2_ctx ctx, const double* F_dev, int64_t n,
+                          int64_t ldf, double lambda_min, double lambda_max,
+                          int64_t n_occ, const sp2_options* opt);
+
+/* Runs Alg. 2 to the stop: the affine start, then one fused symmetric square
+ * per step (the kernel's epilogue applies the chosen polynomial, the
+ * truncation, and accumulates Tr X, Tr X^2 and ||X - X^2||_F^2 in FP64), and
+ * the FP64 stop test on the device. Returns once the stream has finished the
+ * run. Returns SP2_OK when the stop fired (or v_k == 0, or n_occ is 0 or n),
+ * SP2_NOT_CONVERGED after max_iter squares, SP2_DIVERGED, or an error.
+ * sp2_get_* report the outcome in every one of these cases. */
+sp2_status sp2_run(sp2_ctx ctx);
+
+/* Copies the returned iterate X~_n (n x n) to D_dev with leading dimension
+ * ldd >= n: as FP64 when as_fp64 != 0, else in the storage precision (FP64
+ * for SP2_FP64, FP32 for SP2_FP32 and SP2_BF16X3). Ordered on the stream and
+ * synchronised before returning. After SP2_NOT_CONVERGED the iterate is
+ * X~_{max_iter}. Errors: SP2_BAD_STATE before a completed run,
+ * SP2_INVALID_ARG, SP2_HIP_ERROR. */
+sp2_status sp2_get_density(sp2_ctx ctx, void* D_dev, int64_t ldd,
+                           int32_t as_fp64);
+
+/* Outcome of the last run: n_iter = n (index of the returned iterate),
+ * n_squares = number of matrix squares computed, run_ms = device time of
+ * sp2_run from the first kernel to the last, measured with HIP events.
+ * Any pointer may be NULL. Errors: SP2_BAD_STATE before a run. */
+sp2_status sp2_get_info(sp2_ctx ctx, int32_t* n_iter, int32_t* n_squares,
+                        double* run_ms);
+
+/* Per-step history of the last run, host arrays of capacity `cap`:
+ * v[k] = ||X~_k - X~_k^2||_F for k = 0..n_squares-1; t1[k] = Tr X~_k and
+ * t2[k] = ||X~_k||_F^2 = Tr X~_k^2 for k = 0..n_squares (t1/t2 of the iterate
+ * of the last square is included when it was formed); p[k] = polynomial of
+ * step k (1 = x^2, 0 = 2x - x^2; p[0] = -1); r[k] = observed order
+ * log(v_k/C)/log(v_{k-2}) or NaN where undefined. *len receives the number of
+ * valid v entries (= n_squares); t1, t2 and p hold up to n_squares + 1
+ * entries. Arrays shorter than needed are filled up to cap. Any array
+ * pointer may be NULL. */
+sp2_status sp2_get_history(sp2_ctx ctx, int32_t cap, int32_t* len, double* v,
+                           double* t1, double* t2, int8_t* p, double* r);
+
+/* Device durations (milliseconds, from HIP events on the context's stream)
+ * of the square kernels of the last run whose options set kernel_timing:
+ * ms[i] for the square of step i + 1, i = 0..n_squares-1. *len receives
+ * n_squares. ms may be NULL. Errors: SP2_BAD_STATE when the last run did not
+ * record timings. */
+sp2_status sp2_get_kernel_times(sp2_ctx ctx, int32_t cap, int32_t* len,
+                                float* ms);
+
+/* Returns 1 when `tile` is a macro-tile edge the square kernels support for
+ * `precision`, else 0. */
+int32_t sp2_tile_supported(int32_t precision, int32_t tile);
+
+/* Static description of a status code. */
+const char* sp2_status_string(sp2_status s);
+
+/* Text of the last error recorded on the context (empty if none). The
+ * pointer stays valid until the next call on the context. */
+const char* sp2_last_error(sp2_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SP2_H */

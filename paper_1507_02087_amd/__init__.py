@@ -1,0 +1,253 @@
+"""Python binding of libsp2.so, the gfx950 SP2 density-matrix purification
+library (C ABI in include/sp2.h).
+
+The binding only marshals arguments: every step of the purification runs in
+the library's HIP kernels. PyTorch supplies device memory and the HIP stream.
+There is no CPU fallback: if libsp2.so is missing or no GPU is visible the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsp2.so")
+
+# sp2_status
+OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, DIVERGED, BAD_STATE = range(7)
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP_ERROR",
+                4: "NOT_CONVERGED", 5: "DIVERGED", 6: "BAD_STATE"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+BRANCHES = {"nearest": 0, "literal": 1}
+MAX_ITER_LIMIT = 200
+
+# Exported entry points and their ctypes signatures (mirrors include/sp2.h).
+_c = ctypes
+SIGNATURES = {
+    "sp2_default_options": (None, [_c.c_void_p]),
+    "sp2_create": (_c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int, _c.c_void_p]),
+    "sp2_destroy": (_c.c_int, [_c.c_void_p]),
+    "sp2_init_dense": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int64,
+                                  _c.c_double, _c.c_double, _c.c_int64, _c.c_void_p]),
+    "sp2_run": (_c.c_int, [_c.c_void_p]),
+    "sp2_get_density": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_int64, _c.c_int32]),
+    "sp2_get_info": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int32),
+                                _c.POINTER(_c.c_int32), _c.POINTER(_c.c_double)]),
+    "sp2_get_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
+                                   _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                   _c.c_void_p, _c.c_void_p]),
+    "sp2_get_kernel_times": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
+                                        _c.c_void_p]),
+    "sp2_tile_supported": (_c.c_int32, [_c.c_int32, _c.c_int32]),
+    "sp2_status_string": (_c.c_char_p, [_c.c_int]),
+    "sp2_last_error": (_c.c_char_p, [_c.c_void_p]),
+}
+
+
+class Options(ctypes.Structure):
+    """sp2_options."""
+    _fields_ = [("precision", ctypes.c_int32), ("branch", ctypes.c_int32),
+                ("trunc_tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("kernel_timing", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libsp2.so and declares every signature; raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SP2Error(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}"
+                         + (f" ({detail})" if detail else ""))
+
+
+@dataclass
+class Result:
+    """Outcome of one run."""
+    D: object                 # torch.Tensor (n, n) on the device
+    status: int
+    n: int                    # index of the returned iterate X~_n
+    n_squares: int
+    run_ms: float
+    v: list = field(default_factory=list)
+    t1: list = field(default_factory=list)
+    t2: list = field(default_factory=list)
+    p: list = field(default_factory=list)
+    r: list = field(default_factory=list)
+
+    @property
+    def status_name(self) -> str:
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Context:
+    """An sp2_ctx bound to one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the SP2 library has no CPU path")
+        self._lib = load_library()
+        self.device = device
+        with torch.cuda.device(device):
+            self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        st = self._lib.sp2_create(ctypes.byref(h), device,
+                                  ctypes.c_void_p(_stream_handle(self._stream)))
+        if st != OK:
+            raise SP2Error(st, "sp2_create")
+        self._h = h
+        self._n = 0
+        self._prec = "fp64"
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sp2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _err(self) -> str:
+        s = self._lib.sp2_last_error(self._h)
+        return s.decode() if s else ""
+
+    def _check(self, st: int, where: str, ok=(OK,)):
+        if st not in ok:
+            raise SP2Error(st, where, self._err())
+        return st
+
+    # -- C ABI wrappers (same names as the library, minus the prefix) -----
+    def init_dense(self, F, lambda_min: float, lambda_max: float, n_occ: int,
+                   precision: str = "fp64", branch: str = "nearest",
+                   trunc_tau: float = 0.0, max_iter: int = 100, tile: int = 0,
+                   kernel_timing: bool = False):
+        import torch
+        if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
+            raise TypeError("F must be a float64 CUDA tensor")
+        if F.dim() != 2 or F.shape[0] != F.shape[1] or F.stride(1) != 1:
+            raise ValueError("F must be square with unit column stride")
+        opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
+                      int(max_iter), int(tile), 1 if kernel_timing else 0)
+        self._F = F   # keep alive until run() returns
+        st = self._lib.sp2_init_dense(self._h, ctypes.c_void_p(F.data_ptr()),
+                                      F.shape[0], F.stride(0), float(lambda_min),
+                                      float(lambda_max), int(n_occ),
+                                      ctypes.byref(opt))
+        self._check(st, "sp2_init_dense")
+        self._n = F.shape[0]
+        self._prec = precision
+
+    def run(self) -> int:
+        st = self._lib.sp2_run(self._h)
+        return self._check(st, "sp2_run", ok=(OK, NOT_CONVERGED, DIVERGED))
+
+    def get_density(self, out=None, as_fp64: bool = True):
+        import torch
+        n = self._n
+        if out is None:
+            dt = torch.float64 if (as_fp64 or self._prec == "fp64") else torch.float32
+            out = torch.empty((n, n), dtype=dt, device=f"cuda:{self.device}")
+        st = self._lib.sp2_get_density(self._h, ctypes.c_void_p(out.data_ptr()),
+                                       out.stride(0), 1 if as_fp64 else 0)
+        self._check(st, "sp2_get_density")
+        return out
+
+    def get_info(self):
+        n = ctypes.c_int32()
+        sq = ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._check(self._lib.sp2_get_info(self._h, ctypes.byref(n), ctypes.byref(sq),
+                                           ctypes.byref(ms)), "sp2_get_info")
+        return n.value, sq.value, ms.value
+
+    def get_kernel_times(self):
+        """Square-kernel durations (ms) of the last run with kernel_timing."""
+        import numpy as np
+        ln = ctypes.c_int32()
+        buf = np.zeros(MAX_ITER_LIMIT + 1, dtype=np.float32)
+        self._check(self._lib.sp2_get_kernel_times(self._h, buf.size, ctypes.byref(ln),
+                                                   ctypes.c_void_p(buf.ctypes.data)),
+                    "sp2_get_kernel_times")
+        return buf[:ln.value].astype(float).tolist()
+
+    def get_history(self, cap: int = MAX_ITER_LIMIT + 2):
+        import numpy as np
+        ln = ctypes.c_int32()
+        v = np.full(cap, np.nan)
+        t1 = np.full(cap, np.nan)
+        t2 = np.full(cap, np.nan)
+        r = np.full(cap, np.nan)
+        p = np.full(cap, -1, dtype=np.int8)
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+        self._check(self._lib.sp2_get_history(self._h, cap, ctypes.byref(ln), ptr(v),
+                                              ptr(t1), ptr(t2), ptr(p), ptr(r)),
+                    "sp2_get_history")
+        m = ln.value
+        return dict(v=v[:m].tolist(), r=r[:m].tolist(), t1=t1[:m + 1].tolist(),
+                    t2=t2[:m + 1].tolist(), p=p[:m + 1].astype(int).tolist())
+
+
+def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
+              precision: str = "fp64", branch: str = "nearest",
+              trunc_tau: float = 0.0, max_iter: int = 100, tile: int = 0,
+              as_fp64: bool = True, ctx: Context | None = None) -> Result:
+    """SP2 (Alg. 2) on the GPU from F to the converged density matrix."""
+    own = ctx is None
+    if own:
+        ctx = Context(F.device.index or 0)
+    try:
+        ctx.init_dense(F, lambda_min, lambda_max, n_occ, precision, branch,
+                       trunc_tau, max_iter, tile)
+        st = ctx.run()
+        D = ctx.get_density(as_fp64=as_fp64)
+        n, sq, ms = ctx.get_info()
+        h = ctx.get_history()
+        return Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, **h)
+    finally:
+        if own:
+            ctx.close()
+
+
+def status_string(st: int) -> str:
+    return load_library().sp2_status_string(st).decode()
+
+
+def tile_supported(precision: str, tile: int) -> bool:
+    return bool(load_library().sp2_tile_supported(PRECISIONS[precision], tile))
+

@@ -1,0 +1,57 @@
+"""The C-ABI library loads and exports every entry point include/sp2.h
+declares (no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sp2.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sp2_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("sp2_create", "sp2_destroy", "sp2_init_dense", "sp2_run",
+                 "sp2_get_density", "sp2_get_info", "sp2_get_history"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1507_02087_amd as sp2
+    if not os.path.exists(sp2.LIB_PATH):
+        pytest.fail("libsp2.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(sp2.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # the binding declares exactly the header's entry points
+    assert sorted(sp2.SIGNATURES) == declared_functions()
+    sp2.load_library()
+
+
+def test_status_codes_match_oracle():
+    import oracle
+    import paper_1507_02087_amd as sp2
+    for st in oracle.Status:
+        assert sp2.STATUS_NAMES[int(st)] == st.name
+    lib = sp2.load_library()
+    for code, name in sp2.STATUS_NAMES.items():
+        assert lib.sp2_status_string(code).decode() == "SP2_" + name
+
+
+def test_default_options_and_tiles():
+    import paper_1507_02087_amd as sp2
+    lib = sp2.load_library()
+    opt = sp2.Options()
+    lib.sp2_default_options(ctypes.byref(opt))
+    assert (opt.precision, opt.branch, opt.trunc_tau, opt.max_iter, opt.tile,
+            opt.kernel_timing) == (0, 0, 0.0, 100, 0, 0)
+    assert sp2.tile_supported("fp64", 128)
+    assert not sp2.tile_supported("fp64", 100)
+    assert ctypes.sizeof(sp2.Options) == 32
