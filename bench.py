@@ -81,7 +81,8 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-squares", type=int, default=5)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--config", type=int, default=0,
+                    help="square-kernel configuration id (0 = library choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -110,7 +111,8 @@ def main() -> int:
 
     def one_run(prec, timing=False):
         ctx.init_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,
-                       precision=prec, tile=args.tile, kernel_timing=timing)
+                       precision=prec, kernel_config=args.config if prec == args.precision else 0,
+                       kernel_timing=timing)
         st = ctx.run()
         n_it, n_sq, run_ms = ctx.get_info()
         ktimes = ctx.get_kernel_times() if timing else []

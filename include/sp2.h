@@ -88,9 +88,13 @@ typedef struct {
                          after every polynomial step (sec. 5) */
   int32_t max_iter;   /* at most this many squares; 0 selects 100; must be
                          <= SP2_MAX_ITER_LIMIT */
-  int32_t tile;       /* macro-tile edge of the square kernel; 0 lets the
-                         library choose; otherwise one of the sizes the
-                         library reports through sp2_tile_supported */
+  int32_t kernel_config; /* square-kernel configuration: 0 lets the library
+                            choose; otherwise a 1-based id from
+                            sp2_kernel_config_info whose precision matches */
+  int32_t tail_split;  /* tiles of an incomplete last round of workgroups are
+                          split along k into pieces summed by a second
+                          kernel: 0 = automatic, 1 = never, k >= 2 = k pieces
+                          (at most 64) */
   int32_t kernel_timing; /* nonzero: bracket every square launch with a pair
                             of HIP timing events (read back through
                             sp2_get_kernel_times); adds a few microseconds
@@ -98,7 +102,8 @@ typedef struct {
 } sp2_options;
 
 /* Fills *opt with the defaults: SP2_FP64, SP2_BRANCH_NEAREST, no truncation,
- * max_iter 100, tile 0, no kernel timing. */
+ * max_iter 100, automatic kernel configuration and tail split, no kernel
+ * timing. */
 void sp2_default_options(sp2_options* opt);
 
 /* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -162,16 +167,66 @@ sp2_status sp2_get_history(sp2_ctx ctx, int32_t cap, int32_t* len, double* v,
                            double* t1, double* t2, int8_t* p, double* r);
 
 /* Device durations (milliseconds, from HIP events on the context's stream)
- * of the square kernels of the last run whose options set kernel_timing:
- * ms[i] for the square of step i + 1, i = 0..n_squares-1. *len receives
- * n_squares. ms may be NULL. Errors: SP2_BAD_STATE when the last run did not
- * record timings. */
+ * of the square launches of the last run whose options set kernel_timing:
+ * ms[i] covers every square kernel of step i + 1 (all instances), for the
+ * steps of the longest instance. *len receives that step count. ms may be
+ * NULL. Errors: SP2_BAD_STATE when the last run did not record timings. */
 sp2_status sp2_get_kernel_times(sp2_ctx ctx, int32_t cap, int32_t* len,
                                 float* ms);
 
-/* Returns 1 when `tile` is a macro-tile edge the square kernels support for
- * `precision`, else 0. */
-int32_t sp2_tile_supported(int32_t precision, int32_t tile);
+/* ---- Batched purification: many independent matrices, one launch
+ * sequence per step, each instance with its own polynomial choices and its
+ * own stop (Alg. 2 applied to every instance). A dense run (sp2_init_dense)
+ * is a batch of one. ---- */
+
+/* Prepares `count` independent runs. F_dev, n, ldf, lambda_min, lambda_max
+ * and n_occ are host arrays of length count; F_dev[b] is a device pointer to
+ * instance b's n[b] x n[b] FP64 matrix (row-major, leading dimension
+ * ldf[b]), which must stay valid until sp2_batch_run returns. Every instance
+ * obeys the sp2_init_dense rules; the options apply to all instances
+ * (kernel_config 0 lets the library pick a configuration per instance
+ * size). Instances are padded to their tile size and share two iterate
+ * pools. Errors: SP2_INVALID_ARG (the message names the instance),
+ * SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. */
+sp2_status sp2_batch_init(sp2_ctx ctx, int32_t count,
+                          const double* const* F_dev, const int64_t* n,
+                          const int64_t* ldf, const double* lambda_min,
+                          const double* lambda_max, const int64_t* n_occ,
+                          const sp2_options* opt);
+
+/* Runs every instance to its own stop; returns SP2_OK once all instances
+ * have an outcome (each instance's status, including SP2_NOT_CONVERGED and
+ * SP2_DIVERGED, is read with sp2_batch_get), or an error of the run. */
+sp2_status sp2_batch_run(sp2_ctx ctx);
+
+/* Outcome of instance idx of the last batch run: n_iter, n_squares and its
+ * status (an sp2_status value); when D_dev is not NULL also copies its
+ * returned iterate X~_n like sp2_get_density. Any output pointer may be
+ * NULL. Errors: SP2_BAD_STATE before a run, SP2_INVALID_ARG. */
+sp2_status sp2_batch_get(sp2_ctx ctx, int32_t idx, void* D_dev, int64_t ldd,
+                         int32_t as_fp64, int32_t* n_iter, int32_t* n_squares,
+                         int32_t* status);
+
+/* History of instance idx, with the conventions of sp2_get_history. */
+sp2_status sp2_batch_get_history(sp2_ctx ctx, int32_t idx, int32_t cap,
+                                 int32_t* len, double* v, double* t1,
+                                 double* t2, int8_t* p, double* r);
+
+/* Device time of the last run (HIP events, first kernel to last) and the
+ * number of steps of its longest instance. Either pointer may be NULL. */
+sp2_status sp2_batch_get_run_time(sp2_ctx ctx, double* run_ms,
+                                  int32_t* steps);
+
+/* Number of compiled square-kernel configurations (ids 1..count). */
+int32_t sp2_kernel_config_count(void);
+
+/* Describes configuration `id` (1-based): its precision, macro-tile edge
+ * (rows and columns of S per workgroup), waves along rows and columns, and
+ * the K slice staged per LDS buffer. Any output pointer may be NULL.
+ * Errors: SP2_INVALID_ARG for an unknown id. */
+sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
+                                  int32_t* tile, int32_t* waves_m,
+                                  int32_t* waves_n, int32_t* k_slice);
 
 /* Static description of a status code. */
 const char* sp2_status_string(sp2_status s);

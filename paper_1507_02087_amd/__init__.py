@@ -40,7 +40,21 @@ SIGNATURES = {
                                    _c.c_void_p, _c.c_void_p]),
     "sp2_get_kernel_times": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
                                         _c.c_void_p]),
-    "sp2_tile_supported": (_c.c_int32, [_c.c_int32, _c.c_int32]),
+    "sp2_batch_init": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_void_p]),
+    "sp2_batch_run": (_c.c_int, [_c.c_void_p]),
+    "sp2_batch_get": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_int64,
+                                 _c.c_int32, _c.POINTER(_c.c_int32),
+                                 _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "sp2_batch_get_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
+                                         _c.POINTER(_c.c_int32), _c.c_void_p,
+                                         _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                         _c.c_void_p]),
+    "sp2_batch_get_run_time": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double),
+                                          _c.POINTER(_c.c_int32)]),
+    "sp2_kernel_config_count": (_c.c_int32, []),
+    "sp2_kernel_config_info": (_c.c_int, [_c.c_int32] + [_c.POINTER(_c.c_int32)] * 5),
     "sp2_status_string": (_c.c_char_p, [_c.c_int]),
     "sp2_last_error": (_c.c_char_p, [_c.c_void_p]),
 }
@@ -50,17 +64,25 @@ class Options(ctypes.Structure):
     """sp2_options."""
     _fields_ = [("precision", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("trunc_tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("kernel_timing", ctypes.c_int32)]
+                ("kernel_config", ctypes.c_int32), ("tail_split", ctypes.c_int32),
+                ("kernel_timing", ctypes.c_int32)]
 
 
 _lib = None
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Loads libsp2.so and declares every signature; raises if it is absent."""
+    """Loads libsp2.so and declares every signature; raises if it is absent.
+
+    torch is imported first: its bundled HIP runtime then answers
+    libsp2.so's dependency on libamdhip64.so.7 (same SONAME), so the library
+    and torch share one HIP runtime, and with it device pointers and
+    streams. Loading libsp2.so first would map the system runtime and torch
+    would later map a second one."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (see above)
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
@@ -155,7 +177,8 @@ class Context:
     # -- C ABI wrappers (same names as the library, minus the prefix) -----
     def init_dense(self, F, lambda_min: float, lambda_max: float, n_occ: int,
                    precision: str = "fp64", branch: str = "nearest",
-                   trunc_tau: float = 0.0, max_iter: int = 100, tile: int = 0,
+                   trunc_tau: float = 0.0, max_iter: int = 100,
+                   kernel_config: int = 0, tail_split: int = 0,
                    kernel_timing: bool = False):
         import torch
         if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
@@ -163,7 +186,8 @@ class Context:
         if F.dim() != 2 or F.shape[0] != F.shape[1] or F.stride(1) != 1:
             raise ValueError("F must be square with unit column stride")
         opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
-                      int(max_iter), int(tile), 1 if kernel_timing else 0)
+                      int(max_iter), int(kernel_config), int(tail_split),
+                      1 if kernel_timing else 0)
         self._F = F   # keep alive until run() returns
         st = self._lib.sp2_init_dense(self._h, ctypes.c_void_p(F.data_ptr()),
                                       F.shape[0], F.stride(0), float(lambda_min),
@@ -223,9 +247,103 @@ class Context:
                     t2=t2[:m + 1].tolist(), p=p[:m + 1].astype(int).tolist())
 
 
+def _arr(ctype, vals):
+    return (ctype * len(vals))(*vals)
+
+
+class BatchContext(Context):
+    """A context running many independent instances per launch sequence."""
+
+    def batch_init(self, Fs, lambda_min, lambda_max, n_occ, precision: str = "fp64",
+                   branch: str = "nearest", trunc_tau: float = 0.0,
+                   max_iter: int = 100, kernel_config: int = 0, tail_split: int = 0,
+                   kernel_timing: bool = False):
+        import torch
+        for F in Fs:
+            if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
+                raise TypeError("every F must be a float64 CUDA tensor")
+            if F.dim() != 2 or F.shape[0] != F.shape[1] or F.stride(1) != 1:
+                raise ValueError("every F must be square with unit column stride")
+        cnt = len(Fs)
+        opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
+                      int(max_iter), int(kernel_config), int(tail_split),
+                      1 if kernel_timing else 0)
+        self._Fs = list(Fs)   # keep alive until batch_run() returns
+        ptrs = _arr(ctypes.c_void_p, [F.data_ptr() for F in Fs])
+        ns = _arr(ctypes.c_int64, [F.shape[0] for F in Fs])
+        lds = _arr(ctypes.c_int64, [F.stride(0) for F in Fs])
+        lo = _arr(ctypes.c_double, [float(x) for x in lambda_min])
+        hi = _arr(ctypes.c_double, [float(x) for x in lambda_max])
+        no = _arr(ctypes.c_int64, [int(x) for x in n_occ])
+        st = self._lib.sp2_batch_init(self._h, cnt, ptrs, ns, lds, lo, hi, no,
+                                      ctypes.byref(opt))
+        self._check(st, "sp2_batch_init")
+        self._ns = [F.shape[0] for F in Fs]
+        self._prec = precision
+
+    def batch_run(self) -> int:
+        return self._check(self._lib.sp2_batch_run(self._h), "sp2_batch_run")
+
+    def batch_get(self, idx: int, as_fp64: bool = True, with_density: bool = True):
+        import torch
+        n = self._ns[idx]
+        out = None
+        if with_density:
+            dt = torch.float64 if (as_fp64 or self._prec == "fp64") else torch.float32
+            out = torch.empty((n, n), dtype=dt, device=f"cuda:{self.device}")
+        it, sq, stt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.sp2_batch_get(
+            self._h, idx, ctypes.c_void_p(out.data_ptr() if out is not None else 0),
+            n, 1 if as_fp64 else 0, ctypes.byref(it), ctypes.byref(sq),
+            ctypes.byref(stt)), "sp2_batch_get")
+        return out, stt.value, it.value, sq.value
+
+    def batch_history(self, idx: int, cap: int = MAX_ITER_LIMIT + 2):
+        import numpy as np
+        ln = ctypes.c_int32()
+        v, t1, t2, r = (np.full(cap, np.nan) for _ in range(4))
+        p = np.full(cap, -1, dtype=np.int8)
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+        self._check(self._lib.sp2_batch_get_history(
+            self._h, idx, cap, ctypes.byref(ln), ptr(v), ptr(t1), ptr(t2), ptr(p),
+            ptr(r)), "sp2_batch_get_history")
+        m = ln.value
+        return dict(v=v[:m].tolist(), r=r[:m].tolist(), t1=t1[:m + 1].tolist(),
+                    t2=t2[:m + 1].tolist(), p=p[:m + 1].astype(int).tolist())
+
+    def batch_run_time(self):
+        ms, steps = ctypes.c_double(), ctypes.c_int32()
+        self._check(self._lib.sp2_batch_get_run_time(self._h, ctypes.byref(ms),
+                                                     ctypes.byref(steps)),
+                    "sp2_batch_get_run_time")
+        return ms.value, steps.value
+
+
+def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None,
+              as_fp64: bool = True, **opts):
+    """SP2 on many independent matrices at once; returns (results, run_ms)."""
+    own = ctx is None
+    if own:
+        ctx = BatchContext(Fs[0].device.index or 0)
+    try:
+        ctx.batch_init(Fs, lambda_min, lambda_max, n_occ, **opts)
+        ctx.batch_run()
+        ms, _ = ctx.batch_run_time()
+        out = []
+        for b in range(len(Fs)):
+            D, st, n, sq = ctx.batch_get(b, as_fp64=as_fp64)
+            out.append(Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms,
+                              **ctx.batch_history(b)))
+        return out, ms
+    finally:
+        if own:
+            ctx.close()
+
+
 def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
               precision: str = "fp64", branch: str = "nearest",
-              trunc_tau: float = 0.0, max_iter: int = 100, tile: int = 0,
+              trunc_tau: float = 0.0, max_iter: int = 100,
+              kernel_config: int = 0, tail_split: int = 0,
               as_fp64: bool = True, ctx: Context | None = None) -> Result:
     """SP2 (Alg. 2) on the GPU from F to the converged density matrix."""
     own = ctx is None
@@ -233,7 +351,7 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
         ctx = Context(F.device.index or 0)
     try:
         ctx.init_dense(F, lambda_min, lambda_max, n_occ, precision, branch,
-                       trunc_tau, max_iter, tile)
+                       trunc_tau, max_iter, kernel_config, tail_split)
         st = ctx.run()
         D = ctx.get_density(as_fp64=as_fp64)
         n, sq, ms = ctx.get_info()
@@ -248,6 +366,18 @@ def status_string(st: int) -> str:
     return load_library().sp2_status_string(st).decode()
 
 
-def tile_supported(precision: str, tile: int) -> bool:
-    return bool(load_library().sp2_tile_supported(PRECISIONS[precision], tile))
-
+def kernel_configs():
+    """All compiled square-kernel configurations: list of dicts with the
+    1-based id, precision name, macro tile, waves and K slice."""
+    lib = load_library()
+    names = {v: k for k, v in PRECISIONS.items()}
+    out = []
+    for i in range(1, lib.sp2_kernel_config_count() + 1):
+        vals = [ctypes.c_int32() for _ in range(5)]
+        st = lib.sp2_kernel_config_info(i, *[ctypes.byref(v) for v in vals])
+        if st != OK:
+            raise SP2Error(st, "sp2_kernel_config_info")
+        prec, tile, wm, wn, bk = (v.value for v in vals)
+        out.append(dict(id=i, precision=names[prec], tile=tile, waves_m=wm,
+                        waves_n=wn, k_slice=bk))
+    return out

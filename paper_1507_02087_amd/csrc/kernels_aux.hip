@@ -48,37 +48,52 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c,
   }
 }
 
-__global__ __launch_bounds__(kThreads) void state_reset_kernel(DevState* st) {
-  // Clears the whole state with vector stores; one block.
-  int32_t* w = reinterpret_cast<int32_t*>(st);
+// Clears the states of `count` instances and the batch's done counter.
+__global__ __launch_bounds__(kThreads) void state_reset_kernel(DevState* st,
+                                                               int count,
+                                                               int32_t* ndone) {
+  DevState* me = st + blockIdx.x;
+  int32_t* w = reinterpret_cast<int32_t*>(me);
   const int words = static_cast<int>(sizeof(DevState) / sizeof(int32_t));
   for (int i = threadIdx.x; i < words; i += kThreads) w[i] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) st->p[0] = -1;
+  if (threadIdx.x == 0) {
+    me->p[0] = -1;
+    if (blockIdx.x == 0) *ndone = 0;
+  }
 }
 
 // X_0 = (lambda_max I - F) / (lambda_max - lambda_min) in FP64 (Alg. 2),
 // truncated (|x| < tau -> 0, sec. 5), rounded to the storage type, with the
-// padding region set to zero. Each block handles `rows` consecutive rows of
-// the padded matrix and writes one partial triple (0, Tr, sum x^2).
+// padding region set to zero; X_0 = 0 or I when n_occ is 0 or n. Each block
+// handles kF0Rows rows of one instance and writes one partial triple
+// (0, Tr, sum x^2).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void f0_kernel(
-    const double* __restrict__ F, int64_t ldf, int n, int np, double lmax,
-    double width, double tau, T* __restrict__ X, double* __restrict__ part,
-    int rows) {
+    const Instance* __restrict__ insts, const F0Item* __restrict__ items,
+    double* __restrict__ part) {
   __shared__ double sh[kThreads / 64][3];
+  const F0Item it = items[blockIdx.x];
+  const Instance& in = insts[it.inst];
+  const int n = in.n, np = in.ld;
+  const int n_occ = static_cast<int>(in.prm.n_occ);
+  const int trivial = (n_occ == 0) ? 1 : (n_occ == n ? 2 : 0);
+  T* X = static_cast<T*>(in.X[0]);
   double t1 = 0.0, t2 = 0.0;
-  const int r0 = blockIdx.x * rows;
-  for (int rr = 0; rr < rows; ++rr) {
-    const int i = r0 + rr;
-    const double* Fi = F + static_cast<int64_t>(i) * ldf;
+  for (int rr = 0; rr < kF0Rows; ++rr) {
+    const int i = it.row0 + rr;
+    const double* Fi = in.F + static_cast<int64_t>(i) * in.ldf;
     T* Xi = X + static_cast<int64_t>(i) * np;
     for (int j = threadIdx.x; j < np; j += kThreads) {
       double x = 0.0;
       if (i < n && j < n) {
-        const double f = Fi[j];
-        x = ((i == j) ? lmax - f : -f) / width;
-        if (fabs(x) < tau) x = 0.0;
+        if (trivial) {
+          x = (trivial == 2 && i == j) ? 1.0 : 0.0;
+        } else {
+          const double f = Fi[j];
+          x = ((i == j) ? in.lmax - f : -f) / in.width;
+          if (fabs(x) < in.tau) x = 0.0;
+        }
       }
       const T xs = static_cast<T>(x);
       const double xd = static_cast<double>(xs);
@@ -96,47 +111,56 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   }
 }
 
-__device__ __forceinline__ void publish(DevState* st, HostMirror* m,
-                                        int status, int n) {
+__device__ __forceinline__ void publish(DevState* st, int32_t* ndone,
+                                        int count, HostMirror* m, int status,
+                                        int n) {
   st->status = status;
   st->n = n;
   st->done = 1;
-  if (m) {
-    __hip_atomic_store(&m->status, status, __ATOMIC_RELAXED,
+  __threadfence();
+  const int before = atomicAdd(ndone, 1);
+  if (before == count - 1 && m)
+    __hip_atomic_store(&m->all_done, 1, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&m->n, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&m->squares, st->squares, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&m->done, 1, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-  }
 }
 
-// Sums the partial triples of step `iter` in a fixed order and applies the
-// scalar part of Alg. 2 on one thread:
-//   iter == 0: Tr X~_0, Tr X~_0^2; divergence check; choose p_1.
+// One block per instance: sums the instance's partial triples of step
+// `iter` in a fixed order and applies the scalar part of Alg. 2 on one
+// thread:
+//   iter == 0: Tr X~_0, Tr X~_0^2; divergence check; choose p_1 (an
+//     instance with n_occ = 0 or n stops here with n = 0).
 //   iter >= 1: v_{iter-1} from the square of X~_{iter-1}; Tr/Tr^2 of X~_iter;
 //     stop test at k = iter - 1; divergence; max_iter; choose p_{iter+1}.
 __global__ __launch_bounds__(kThreads) void finalize_kernel(
-    const double* __restrict__ part, int count, DevState* st,
-    HostMirror* mirror, int iter, StopParams prm) {
+    const Instance* __restrict__ insts, int count,
+    const double* __restrict__ part, const double* __restrict__ part_f0,
+    int32_t* ndone, HostMirror* mirror, int iter) {
   __shared__ double sh[kThreads / 64][3];
+  const Instance& in = insts[blockIdx.x];
+  DevState* st = in.st;
   if (st->done) return;
+  const double* pp = (iter == 0) ? part_f0 + 3 * in.f0blk0 : part + 3 * in.tile0;
+  const int cnt = (iter == 0) ? in.nf0blk : in.ntiles;
   double a = 0.0, b = 0.0, c = 0.0;
-  for (int i = threadIdx.x; i < count; i += kThreads) {
-    a += part[3 * i + 0];
-    b += part[3 * i + 1];
-    c += part[3 * i + 2];
+  for (int i = threadIdx.x; i < cnt; i += kThreads) {
+    a += pp[3 * i + 0];
+    b += pp[3 * i + 1];
+    c += pp[3 * i + 2];
   }
   block_sum3(a, b, c, sh);
   if (threadIdx.x != 0) return;
 
+  const StopParams& prm = in.prm;
   const double t1 = b, t2 = c;
   st->t1[iter] = t1;
   st->t2[iter] = t2;
   if (iter == 0) {
+    if (prm.n_occ == 0.0 || prm.n_occ == prm.n) {
+      publish(st, ndone, count, mirror, /*OK*/ 0, 0);
+      return;
+    }
     if (!isfinite(t1) || !isfinite(t2)) {
-      publish(st, mirror, /*DIVERGED*/ 5, 0);
+      publish(st, ndone, count, mirror, /*DIVERGED*/ 5, 0);
       return;
     }
   } else {
@@ -152,23 +176,23 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     }
     st->r[k] = r;
     if (!isfinite(vk)) {
-      publish(st, mirror, 5, k);
+      publish(st, ndone, count, mirror, 5, k);
       return;
     }
     if (vk == 0.0) {                          // exactly idempotent
-      publish(st, mirror, 0, k);
+      publish(st, ndone, count, mirror, 0, k);
       return;
     }
     if (k >= 2 && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
-      publish(st, mirror, 0, k);              // Alg. 2 stop
+      publish(st, ndone, count, mirror, 0, k);   // Alg. 2 stop
       return;
     }
     if (!isfinite(t1) || !isfinite(t2) || t2 > t1 + prm.n) {
-      publish(st, mirror, 5, iter);
+      publish(st, ndone, count, mirror, 5, iter);
       return;
     }
     if (iter >= prm.max_iter) {
-      publish(st, mirror, /*NOT_CONVERGED*/ 4, iter);
+      publish(st, ndone, count, mirror, /*NOT_CONVERGED*/ 4, iter);
       return;
     }
   }
@@ -180,17 +204,6 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     pn = (fabs(t2 - prm.n_occ) < fabs(2.0 * t1 - t2 - prm.n_occ)) ? 1 : 0;
   }
   st->p[iter + 1] = static_cast<int8_t>(pn);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void fill_kernel(T* X, int n, int np,
-                                                        int identity) {
-  const int64_t total = static_cast<int64_t>(np) * np;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
-       e < total; e += static_cast<int64_t>(gridDim.x) * kThreads) {
-    const int i = static_cast<int>(e / np), j = static_cast<int>(e % np);
-    X[e] = (identity && i == j && i < n) ? T(1) : T(0);
-  }
 }
 
 template <typename Tin, typename Tout>
@@ -214,43 +227,30 @@ int grid_for(int64_t total) {
 
 }  // namespace
 
-hipError_t launch_state_reset(DevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(state_reset_kernel, dim3(1), dim3(kThreads), 0, s, st);
+hipError_t launch_state_reset(DevState* st, int count, int32_t* ndone,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(state_reset_kernel, dim3(count), dim3(kThreads), 0, s, st,
+                     count, ndone);
   return hipGetLastError();
 }
 
-hipError_t launch_f0(const double* F, int64_t ldf, int n, int np, double lmax,
-                     double width, double tau, void* X0, bool fp64_store,
-                     double* part, int rows_per_block, hipStream_t s) {
-  const int blocks = np / rows_per_block;
+hipError_t launch_f0(const Instance* inst, const F0Item* items, int nitems,
+                     bool fp64_store, double* part_f0, hipStream_t s) {
   if (fp64_store)
-    hipLaunchKernelGGL(f0_kernel<double>, dim3(blocks), dim3(kThreads), 0, s,
-                       F, ldf, n, np, lmax, width, tau,
-                       static_cast<double*>(X0), part, rows_per_block);
+    hipLaunchKernelGGL(f0_kernel<double>, dim3(nitems), dim3(kThreads), 0, s,
+                       inst, items, part_f0);
   else
-    hipLaunchKernelGGL(f0_kernel<float>, dim3(blocks), dim3(kThreads), 0, s,
-                       F, ldf, n, np, lmax, width, tau,
-                       static_cast<float*>(X0), part, rows_per_block);
+    hipLaunchKernelGGL(f0_kernel<float>, dim3(nitems), dim3(kThreads), 0, s,
+                       inst, items, part_f0);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* part, int count, DevState* st,
-                           HostMirror* mirror, int iter, StopParams prm,
+hipError_t launch_finalize(const Instance* inst, int count,
+                           const double* part, const double* part_f0,
+                           int32_t* ndone, HostMirror* mirror, int iter,
                            hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s, part,
-                     count, st, mirror, iter, prm);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill(void* X, bool fp64_store, int n, int np, int identity,
-                       hipStream_t s) {
-  const int g = grid_for(static_cast<int64_t>(np) * np);
-  if (fp64_store)
-    hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(kThreads), 0, s,
-                       static_cast<double*>(X), n, np, identity);
-  else
-    hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(kThreads), 0, s,
-                       static_cast<float*>(X), n, np, identity);
+  hipLaunchKernelGGL(finalize_kernel, dim3(count), dim3(kThreads), 0, s, inst,
+                     count, part, part_f0, ndone, mirror, iter);
   return hipGetLastError();
 }
 

@@ -1,14 +1,17 @@
 // Host driver and C ABI of the SP2 library (see include/sp2.h).
 //
-// A run is a stream-ordered sequence of kernels:
-//   state reset -> f0 (X_0 and its traces) -> finalize(0)
-//   -> for i = 1, 2, ...: square(i) -> finalize(i)
-// The polynomial choice, the stop test and the outcome live in device memory
-// (DevState); the finalize kernel also mirrors the outcome into host-coherent
-// pinned memory. The host keeps up to kLookahead steps queued ahead of the
-// step whose outcome it last observed, so the device never waits on the host;
-// steps queued after the stop return at once because every kernel first
-// reads the device-side done flag.
+// Every run is a batch of instances (sp2_init_dense prepares a batch of
+// one). A run is a stream-ordered sequence of kernels:
+//   state reset -> f0 (X_0 and its traces, all instances) -> finalize(0)
+//   -> for i = 1, 2, ...: square(i) per launch group -> finalize(i)
+// A launch group is the set of instances that share a square-kernel
+// configuration. The polynomial choices, the stop tests and the outcomes
+// live in device memory (one DevState per instance); the finalize kernel
+// counts stopped instances and tells the host, through host-coherent pinned
+// memory, when all have stopped. The host keeps up to kLookahead steps
+// queued ahead of the step whose outcome it last observed, so the device
+// never waits on the host; steps queued after the stop return at once
+// because every kernel first reads its instance's done flag.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -23,12 +26,45 @@
 
 using sp2::DevState;
 using sp2::HostMirror;
+using sp2::Instance;
 
 namespace {
 
 constexpr int kLookahead = 3;
 constexpr int kRing = 8;
-constexpr int kF0Rows = 8;
+
+// Instance as the host keeps it.
+struct HostInst {
+  const double* F = nullptr;
+  int64_t n = 0, ldf = 0, n_occ = 0, np = 0;
+  double lmin = 0.0, lmax = 0.0;
+  int cfg = 0;                 // 0-based kernel configuration id
+  size_t xoff = 0;             // element offset in the iterate pools
+  bool trivial = false;        // n_occ == 0 or n_occ == n
+};
+
+// Instances sharing one kernel configuration, with their work plan.
+struct Group {
+  int cfg = 0;
+  int grid = 0;
+  int ntail = 0, split = 1;
+  sp2::WorkItem* items = nullptr;   // device
+  sp2::TailItem* tails = nullptr;   // device
+  size_t items_cap = 0, tails_cap = 0;
+};
+
+template <typename P>
+hipError_t grow(P*& ptr, size_t& cap, size_t bytes, hipStream_t s) {
+  if (bytes <= cap) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  e = hipMalloc(reinterpret_cast<void**>(&ptr), bytes);
+  if (e == hipSuccess) cap = bytes;
+  return e;
+}
 
 }  // namespace
 
@@ -36,40 +72,45 @@ struct sp2_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  int num_cus = 256;
 
   // problem
-  const double* F = nullptr;
-  int64_t n = 0, ldf = 0, n_occ = 0, np = 0;
-  double lmin = 0.0, lmax = 0.0;
   sp2_options opt{};
-  int tile = 128;
   bool fp64_store = true;
+  std::vector<HostInst> hi;
+  std::vector<Group> groups;
 
-  // workspaces
-  void* X[2] = {nullptr, nullptr};
-  size_t x_bytes = 0;
-  double* part = nullptr;
-  size_t part_count = 0;
-  int2* tiles = nullptr;
-  size_t tiles_cap = 0;
-  int ntiles = 0;
-  int per_xcd = 0;
-  DevState* st = nullptr;
+  // device workspaces
+  void* pool[2] = {nullptr, nullptr};
+  size_t pool_cap[2] = {0, 0};
+  Instance* d_inst = nullptr;
+  size_t d_inst_cap = 0;
+  DevState* d_st = nullptr;
+  size_t d_st_cap = 0;
+  int2* d_tiles = nullptr;
+  size_t d_tiles_cap = 0;
+  double* d_part = nullptr;
+  size_t d_part_cap = 0;
+  double* d_part_f0 = nullptr;
+  size_t d_part_f0_cap = 0;
+  sp2::F0Item* d_f0 = nullptr;
+  size_t d_f0_cap = 0;
+  int nf0 = 0;
+  void* d_ws = nullptr;
+  size_t d_ws_cap = 0;
+  int32_t* d_ndone = nullptr;
   HostMirror* mirror = nullptr;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
   hipEvent_t ev_ring[kRing] = {};
-  std::vector<hipEvent_t> ev_sq;   // pairs around each square when timing
+  std::vector<hipEvent_t> ev_sq;   // pairs around each step's squares
   std::vector<float> square_ms;
   bool timed = false;
 
   // outcome
   bool inited = false, ran = false;
-  sp2_status last = SP2_BAD_STATE;
-  int32_t n_iter = 0, n_squares = 0;
   double run_ms = 0.0;
-  int result_buf = 0;
-  DevState host_state{};
-  bool trivial = false;  // n_occ == 0 or n_occ == n
+  int32_t steps = 0;               // squares of the longest instance
+  std::vector<DevState> host_state;
 };
 
 namespace {
@@ -95,24 +136,92 @@ sp2_status fail(sp2_ctx c, sp2_status s, const char* what, hipError_t e) {
     }                                                                 \
   } while (0)
 
-int default_tile(int precision, int64_t n) {
-  (void)precision;
-  (void)n;
-  return 128;
+// Library choice of square-kernel configuration (0-based id) for one
+// instance of dimension n.
+int default_config(int precision, int64_t n) {
+  switch (precision) {
+    case SP2_FP64: return n >= 1024 ? 0 : 2;
+    case SP2_FP32: return 3;
+    default: return n >= 2048 ? 7 : 6;
+  }
 }
 
 // Upper-triangle tiles (I <= J) of an nt x nt tile grid, ordered by groups of
 // G x G neighbouring tiles so that consecutive list entries share row panels.
-std::vector<int2> build_tile_list(int nt) {
+void append_tile_list(int nt, std::vector<int2>& out) {
   const int G = 4;
-  std::vector<int2> out;
-  out.reserve(static_cast<size_t>(nt) * (nt + 1) / 2);
   for (int gi = 0; gi < nt; gi += G)
     for (int gj = gi; gj < nt; gj += G)
       for (int i = gi; i < gi + G && i < nt; ++i)
         for (int j = gj; j < gj + G && j < nt; ++j)
           if (i <= j) out.push_back(make_int2(i, j));
-  return out;
+}
+
+// Work plan of one launch group.
+struct Plan {
+  std::vector<sp2::WorkItem> items;   // one per workgroup
+  std::vector<sp2::TailItem> tails;
+  int split = 1;
+};
+
+// Given the group's tiles (global slots, owning instance, K slices of each),
+// splits the tiles of an incomplete last round of workgroups into K pieces
+// and deals the work to the 8 XCDs: workgroup b runs on XCD b mod 8, so XCD x
+// receives a contiguous chunk of the (neighbour-grouped) tile list followed
+// by a chunk of the pieces, which keeps the panels its tiles share in its
+// own L2. Pieces are numbered from 0 within the group.
+Plan make_plan(const std::vector<int>& slots, const std::vector<int>& owner,
+               const std::vector<int>& nk, int concurrency, int tail_split) {
+  Plan pl;
+  const int ntiles = static_cast<int>(slots.size());
+  const int rounds = ntiles / concurrency;
+  const int rem = ntiles % concurrency;
+  int min_nk = 1 << 30;
+  for (int k : nk) min_nk = std::min(min_nk, k);
+  int split = 1;
+  if (tail_split >= 2) {
+    split = tail_split;
+  } else if (tail_split == 0 && rem > 0 && 2 * rem <= concurrency) {
+    split = std::min({concurrency / rem, min_nk / 2, 16});
+  }
+  split = std::max(1, std::min(split, min_nk));
+  const int ntail = (split > 1) ? (rounds > 0 ? rem : ntiles) : 0;
+  const int nfull = ntiles - ntail;
+  const int npieces = ntail * split;
+  pl.split = split;
+  for (int t = 0; t < ntail; ++t)
+    pl.tails.push_back(sp2::TailItem{owner[nfull + t], slots[nfull + t],
+                                     t * split, 0});
+  const int X = 8;
+  std::vector<int> f0(X + 1, 0), q0(X + 1, 0);
+  for (int x = 0; x < X; ++x) {
+    f0[x + 1] = f0[x] + nfull / X + (x < nfull % X ? 1 : 0);
+    q0[x + 1] = q0[x] + npieces / X + (x < npieces % X ? 1 : 0);
+  }
+  int per = 0;
+  for (int x = 0; x < X; ++x)
+    per = std::max(per, (f0[x + 1] - f0[x]) + (q0[x + 1] - q0[x]));
+  pl.items.assign(static_cast<size_t>(per) * X,
+                  sp2::WorkItem{0, -1, -1, 0, 0, 0});
+  for (int x = 0; x < X; ++x) {
+    const int nf = f0[x + 1] - f0[x], nq = q0[x + 1] - q0[x];
+    for (int r = 0; r < nf + nq; ++r) {
+      sp2::WorkItem& w = pl.items[static_cast<size_t>(r) * X + x];
+      if (r < nf) {
+        const int t = f0[x] + r;
+        w = sp2::WorkItem{owner[t], slots[t], -1, 0, nk[t], 0};
+      } else {
+        const int q = q0[x] + (r - nf);
+        const int t = nfull + q / split, j = q % split;
+        w = sp2::WorkItem{
+            owner[t], slots[t], q,
+            static_cast<int32_t>(static_cast<int64_t>(j) * nk[t] / split),
+            static_cast<int32_t>(static_cast<int64_t>(j + 1) * nk[t] / split),
+            0};
+      }
+    }
+  }
+  return pl;
 }
 
 sp2_status ensure_events(sp2_ctx c) {
@@ -122,6 +231,284 @@ sp2_status ensure_events(sp2_ctx c) {
   for (int i = 0; i < kRing; ++i)
     SP2_HIP(c, hipEventCreateWithFlags(&c->ev_ring[i], hipEventDisableTiming));
   return SP2_OK;
+}
+
+sp2_status validate_options(sp2_ctx c, sp2_options& opt) {
+  if (opt.max_iter == 0) opt.max_iter = 100;
+  if (opt.precision < SP2_FP64 || opt.precision > SP2_BF16X3)
+    return fail(c, SP2_INVALID_ARG, "unknown precision", hipSuccess);
+  if (opt.branch != SP2_BRANCH_NEAREST && opt.branch != SP2_BRANCH_LITERAL)
+    return fail(c, SP2_INVALID_ARG, "unknown branch rule", hipSuccess);
+  if (!(opt.trunc_tau >= 0.0) || !isfinite(opt.trunc_tau))
+    return fail(c, SP2_INVALID_ARG, "trunc_tau must be finite and >= 0",
+                hipSuccess);
+  if (opt.max_iter < 1 || opt.max_iter > SP2_MAX_ITER_LIMIT)
+    return fail(c, SP2_INVALID_ARG, "max_iter outside [1, SP2_MAX_ITER_LIMIT]",
+                hipSuccess);
+  if (opt.kernel_config != 0) {
+    const sp2::KernelConfig* kc = sp2::kernel_config(opt.kernel_config - 1);
+    if (!kc || kc->precision != opt.precision)
+      return fail(c, SP2_INVALID_ARG,
+                  "kernel_config unknown or of another precision", hipSuccess);
+  }
+  if (opt.tail_split < 0 || opt.tail_split > 64)
+    return fail(c, SP2_INVALID_ARG, "tail_split outside [0, 64]", hipSuccess);
+  return SP2_OK;
+}
+
+sp2_status validate_instance(sp2_ctx c, const double* F, int64_t n, int64_t ldf,
+                             double lmin, double lmax, int64_t n_occ) {
+  if (!F) return fail(c, SP2_INVALID_ARG, "F_dev is NULL", hipSuccess);
+  if (n <= 0 || n > 65536)
+    return fail(c, SP2_INVALID_ARG, "n must be in [1, 65536]", hipSuccess);
+  if (ldf < n) return fail(c, SP2_INVALID_ARG, "ldf < n", hipSuccess);
+  if (n_occ < 0 || n_occ > n)
+    return fail(c, SP2_INVALID_ARG, "n_occ outside [0, n]", hipSuccess);
+  if (!isfinite(lmin) || !isfinite(lmax) || !(lmax > lmin) ||
+      !isfinite(lmax - lmin))
+    return fail(c, SP2_INVALID_ARG,
+                "spectral bounds must be finite with lambda_max > lambda_min",
+                hipSuccess);
+  return SP2_OK;
+}
+
+void release_groups(sp2_ctx c) {
+  for (Group& g : c->groups) {
+    if (g.items) (void)hipFree(g.items);
+    if (g.tails) (void)hipFree(g.tails);
+  }
+  c->groups.clear();
+}
+
+// Builds the instance table, tile table, launch groups and their plans, and
+// (re)allocates every workspace. Instances come in c->hi.
+sp2_status setup(sp2_ctx c) {
+  const int count = static_cast<int>(c->hi.size());
+  const size_t esz = c->fp64_store ? 8 : 4;
+  hipStream_t s = c->stream;
+  // configurations, padding, pool offsets
+  size_t pool_elems = 0;
+  for (HostInst& h : c->hi) {
+    h.cfg = c->opt.kernel_config ? c->opt.kernel_config - 1
+                                 : default_config(c->opt.precision, h.n);
+    const int bm = sp2::kernel_config(h.cfg)->bm;
+    h.np = ((h.n + bm - 1) / bm) * bm;
+    h.xoff = pool_elems;
+    pool_elems += static_cast<size_t>(h.np) * h.np;
+    pool_elems = (pool_elems + 63) / 64 * 64;   // 256-byte aligned starts
+    h.trivial = (h.n_occ == 0 || h.n_occ == h.n);
+  }
+  for (int q = 0; q < 2; ++q)
+    SP2_HIP(c, grow(c->pool[q], c->pool_cap[q], pool_elems * esz, s));
+
+  // instance table, tiles and affine-start blocks
+  SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
+  std::vector<int2> tiles;
+  std::vector<Instance> inst(count);
+  std::vector<sp2::F0Item> f0;
+  for (int b = 0; b < count; ++b) {
+    const HostInst& h = c->hi[b];
+    const int bm = sp2::kernel_config(h.cfg)->bm;
+    Instance& in = inst[b];
+    in.X[0] = static_cast<char*>(c->pool[0]) + h.xoff * esz;
+    in.X[1] = static_cast<char*>(c->pool[1]) + h.xoff * esz;
+    in.F = h.F;
+    in.ldf = h.ldf;
+    in.n = static_cast<int>(h.n);
+    in.ld = static_cast<int>(h.np);
+    in.tile0 = static_cast<int>(tiles.size());
+    append_tile_list(static_cast<int>(h.np / bm), tiles);
+    in.ntiles = static_cast<int>(tiles.size()) - in.tile0;
+    in.f0blk0 = static_cast<int>(f0.size());
+    for (int r = 0; r < h.np; r += sp2::kF0Rows)
+      f0.push_back(sp2::F0Item{b, r});
+    in.nf0blk = static_cast<int>(f0.size()) - in.f0blk0;
+    in.st = c->d_st + b;
+    in.lmax = h.lmax;
+    in.width = h.lmax - h.lmin;
+    in.tau = c->opt.trunc_tau;
+    in.prm.n_occ = static_cast<double>(h.n_occ);
+    in.prm.n = static_cast<double>(h.n);
+    in.prm.branch = c->opt.branch;
+    in.prm.max_iter = c->opt.max_iter;
+  }
+
+  // launch groups: one per configuration in use (trivial instances stop
+  // before any square and get no work)
+  release_groups(c);
+  std::vector<int> cfgs;
+  for (const HostInst& h : c->hi)
+    if (!h.trivial && std::find(cfgs.begin(), cfgs.end(), h.cfg) == cfgs.end())
+      cfgs.push_back(h.cfg);
+  size_t ws_elems = 0;
+  for (int cfg : cfgs) {
+    const sp2::KernelConfig* kc = sp2::kernel_config(cfg);
+    std::vector<int> slots, owner, nk;
+    for (int b = 0; b < count; ++b) {
+      if (c->hi[b].cfg != cfg || c->hi[b].trivial) continue;
+      for (int t = 0; t < inst[b].ntiles; ++t) {
+        slots.push_back(inst[b].tile0 + t);
+        owner.push_back(b);
+        nk.push_back(static_cast<int>(c->hi[b].np / kc->bk));
+      }
+    }
+    Plan pl = make_plan(slots, owner, nk, c->num_cus * kc->occupancy,
+                        c->opt.tail_split);
+    Group g;
+    g.cfg = cfg;
+    g.grid = static_cast<int>(pl.items.size());
+    g.ntail = static_cast<int>(pl.tails.size());
+    g.split = pl.split;
+    // Groups run one after another on the stream, so they share one
+    // workspace sized for the largest.
+    ws_elems = std::max(ws_elems, static_cast<size_t>(g.ntail) * g.split *
+                                      kc->bm * kc->bm);
+    c->groups.push_back(g);
+    Group& gg = c->groups.back();
+    SP2_HIP(c, grow(gg.items, gg.items_cap,
+                    pl.items.size() * sizeof(sp2::WorkItem), s));
+    SP2_HIP(c, hipMemcpyAsync(gg.items, pl.items.data(),
+                              pl.items.size() * sizeof(sp2::WorkItem),
+                              hipMemcpyHostToDevice, s));
+    if (!pl.tails.empty()) {
+      SP2_HIP(c, grow(gg.tails, gg.tails_cap,
+                      pl.tails.size() * sizeof(sp2::TailItem), s));
+      SP2_HIP(c, hipMemcpyAsync(gg.tails, pl.tails.data(),
+                                pl.tails.size() * sizeof(sp2::TailItem),
+                                hipMemcpyHostToDevice, s));
+    }
+    // the copies read host vectors that go out of scope: finish them now
+    SP2_HIP(c, hipStreamSynchronize(s));
+  }
+  if (ws_elems) SP2_HIP(c, grow(c->d_ws, c->d_ws_cap, ws_elems * esz, s));
+  SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, count * sizeof(Instance), s));
+  SP2_HIP(c, grow(c->d_tiles, c->d_tiles_cap,
+                  std::max<size_t>(1, tiles.size()) * sizeof(int2), s));
+  SP2_HIP(c, grow(c->d_part, c->d_part_cap,
+                  std::max<size_t>(1, tiles.size()) * 3 * sizeof(double), s));
+  SP2_HIP(c, grow(c->d_part_f0, c->d_part_f0_cap,
+                  f0.size() * 3 * sizeof(double), s));
+  SP2_HIP(c, grow(c->d_f0, c->d_f0_cap, f0.size() * sizeof(sp2::F0Item), s));
+  SP2_HIP(c, hipMemcpyAsync(c->d_inst, inst.data(), count * sizeof(Instance),
+                            hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    SP2_HIP(c, hipMemcpyAsync(c->d_tiles, tiles.data(),
+                              tiles.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipMemcpyAsync(c->d_f0, f0.data(), f0.size() * sizeof(sp2::F0Item),
+                            hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipStreamSynchronize(s));
+  c->nf0 = static_cast<int>(f0.size());
+  return SP2_OK;
+}
+
+sp2_status run_batch(sp2_ctx c) {
+  SP2_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  const int count = static_cast<int>(c->hi.size());
+  c->mirror->all_done = 0;
+  __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  const bool timing = c->opt.kernel_timing != 0;
+  if (timing && c->ev_sq.empty()) {
+    c->ev_sq.assign(2 * (SP2_MAX_ITER_LIMIT + 1), nullptr);
+    for (hipEvent_t& e : c->ev_sq) SP2_HIP(c, hipEventCreate(&e));
+  }
+  c->timed = false;
+  c->square_ms.clear();
+
+  SP2_HIP(c, hipEventRecord(c->ev_start, s));
+  SP2_HIP(c, sp2::launch_state_reset(c->d_st, count, c->d_ndone, s));
+  SP2_HIP(c, sp2::launch_f0(c->d_inst, c->d_f0, c->nf0, c->fp64_store,
+                            c->d_part_f0, s));
+  SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
+                                  c->d_ndone, c->mirror, 0, s));
+  SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
+
+  sp2::SquareArgs a;
+  a.inst = c->d_inst;
+  a.tiles = c->d_tiles;
+  a.ws = c->d_ws;
+  a.part = c->d_part;
+  int last = 0;
+  for (int i = 1; i <= c->opt.max_iter && !c->groups.empty(); ++i) {
+    if (i > kLookahead)
+      SP2_HIP(c, hipEventSynchronize(c->ev_ring[(i - kLookahead) % kRing]));
+    if (__atomic_load_n(&c->mirror->all_done, __ATOMIC_ACQUIRE)) break;
+    a.iter = i;
+    if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i], s));
+    for (const Group& g : c->groups) {
+      a.items = g.items;
+      a.tails = g.tails;
+      a.ntail = g.ntail;
+      a.split = g.split;
+      SP2_HIP(c, sp2::launch_square(g.cfg, a, g.grid, s));
+    }
+    if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i + 1], s));
+    SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
+                                    c->d_ndone, c->mirror, i, s));
+    SP2_HIP(c, hipEventRecord(c->ev_ring[i % kRing], s));
+    last = i;
+  }
+  SP2_HIP(c, hipEventRecord(c->ev_stop, s));
+  SP2_HIP(c, hipEventSynchronize(c->ev_stop));
+  float ms = 0.f;
+  SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  c->host_state.resize(count);
+  SP2_HIP(c, hipMemcpyAsync(c->host_state.data(), c->d_st,
+                            count * sizeof(DevState), hipMemcpyDeviceToHost,
+                            s));
+  SP2_HIP(c, hipStreamSynchronize(s));
+  int32_t steps = 0;
+  for (const DevState& h : c->host_state) {
+    if (!h.done)
+      return fail(c, SP2_BAD_STATE, "run ended without an outcome", hipSuccess);
+    steps = std::max(steps, h.squares);
+  }
+  c->steps = steps;
+  c->run_ms = ms;
+  if (timing) {
+    for (int i = 1; i <= std::min(steps, last); ++i) {
+      float t = 0.f;
+      SP2_HIP(c, hipEventElapsedTime(&t, c->ev_sq[2 * i], c->ev_sq[2 * i + 1]));
+      c->square_ms.push_back(t);
+    }
+    c->timed = true;
+  }
+  c->ran = true;
+  return SP2_OK;
+}
+
+sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
+                        int32_t as_fp64) {
+  const HostInst& h = c->hi[idx];
+  if (!D_dev || ldd < h.n)
+    return fail(c, SP2_INVALID_ARG, "D_dev NULL or ldd < n", hipSuccess);
+  const DevState& st = c->host_state[idx];
+  const size_t esz = c->fp64_store ? 8 : 4;
+  const void* X = static_cast<const char*>(c->pool[st.n & 1]) + h.xoff * esz;
+  SP2_HIP(c, hipSetDevice(c->device));
+  SP2_HIP(c, sp2::launch_copy_out(X, c->fp64_store, static_cast<int>(h.n),
+                                  static_cast<int>(h.np), D_dev, ldd,
+                                  as_fp64 != 0, c->stream));
+  SP2_HIP(c, hipStreamSynchronize(c->stream));
+  return SP2_OK;
+}
+
+void fill_history(const sp2_ctx c, int idx, int32_t cap, int32_t* len,
+                  double* v, double* t1, double* t2, int8_t* p, double* r) {
+  const DevState& h = c->host_state[idx];
+  const bool trivial = c->hi[idx].trivial;
+  const int nv = trivial ? 0 : h.squares;
+  if (len) *len = nv;
+  // Traces exist for X~_0 .. X~_m where m is the last iterate formed.
+  const int nt = trivial ? 0 : nv + 1;
+  for (int k = 0; k < cap; ++k) {
+    if (v) v[k] = k < nv ? h.v[k] : NAN;
+    if (r) r[k] = k < nv ? h.r[k] : NAN;
+    if (t1) t1[k] = k < nt ? h.t1[k] : NAN;
+    if (t2) t2[k] = k < nt ? h.t2[k] : NAN;
+    if (p) p[k] = k < nt ? (k == 0 ? -1 : h.p[k]) : -1;
+  }
 }
 
 }  // namespace
@@ -134,7 +521,8 @@ void sp2_default_options(sp2_options* opt) {
   opt->branch = SP2_BRANCH_NEAREST;
   opt->trunc_tau = 0.0;
   opt->max_iter = 100;
-  opt->tile = 0;
+  opt->kernel_config = 0;
+  opt->tail_split = 0;
   opt->kernel_timing = 0;
 }
 
@@ -153,9 +541,19 @@ const char* sp2_status_string(sp2_status s) {
 
 const char* sp2_last_error(sp2_ctx ctx) { return ctx ? ctx->err.c_str() : ""; }
 
-int32_t sp2_tile_supported(int32_t precision, int32_t tile) {
-  if (precision < SP2_FP64 || precision > SP2_BF16X3) return 0;
-  return sp2::square_tile_supported(precision, tile) ? 1 : 0;
+int32_t sp2_kernel_config_count(void) { return sp2::kernel_config_count(); }
+
+sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
+                                  int32_t* tile, int32_t* waves_m,
+                                  int32_t* waves_n, int32_t* k_slice) {
+  const sp2::KernelConfig* k = sp2::kernel_config(id - 1);
+  if (!k) return SP2_INVALID_ARG;
+  if (precision) *precision = k->precision;
+  if (tile) *tile = k->bm;
+  if (waves_m) *waves_m = k->wm;
+  if (waves_n) *waves_n = k->wn;
+  if (k_slice) *k_slice = k->bk;
+  return SP2_OK;
 }
 
 sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream) {
@@ -169,7 +567,7 @@ sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream) {
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipSetDevice(device);
-  if (e == hipSuccess) e = hipMalloc(&c->st, sizeof(DevState));
+  if (e == hipSuccess) e = hipMalloc(&c->d_ndone, 256);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&c->mirror), sizeof(HostMirror),
                       hipHostMallocCoherent | hipHostMallocMapped);
@@ -178,6 +576,10 @@ sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream) {
     return e == hipErrorOutOfMemory ? SP2_OUT_OF_MEMORY : SP2_HIP_ERROR;
   }
   memset(c->mirror, 0, sizeof(HostMirror));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess &&
+      prop.multiProcessorCount > 0)
+    c->num_cus = prop.multiProcessorCount;
   if (ensure_events(c) != SP2_OK) {
     sp2_destroy(c);
     return SP2_HIP_ERROR;
@@ -190,11 +592,20 @@ sp2_status sp2_destroy(sp2_ctx c) {
   if (!c) return SP2_OK;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (void* p : c->X)
+  auto rel = [](void* p) {
     if (p) (void)hipFree(p);
-  if (c->part) (void)hipFree(c->part);
-  if (c->tiles) (void)hipFree(c->tiles);
-  if (c->st) (void)hipFree(c->st);
+  };
+  rel(c->pool[0]);
+  rel(c->pool[1]);
+  rel(c->d_inst);
+  rel(c->d_st);
+  rel(c->d_tiles);
+  rel(c->d_part);
+  rel(c->d_part_f0);
+  rel(c->d_f0);
+  rel(c->d_ws);
+  rel(c->d_ndone);
+  release_groups(c);
   if (c->mirror) (void)hipHostFree(c->mirror);
   if (c->ev_start) (void)hipEventDestroy(c->ev_start);
   if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
@@ -206,233 +617,121 @@ sp2_status sp2_destroy(sp2_ctx c) {
   return SP2_OK;
 }
 
-sp2_status sp2_init_dense(sp2_ctx c, const double* F_dev, int64_t n,
-                          int64_t ldf, double lambda_min, double lambda_max,
-                          int64_t n_occ, const sp2_options* opt_in) {
+sp2_status sp2_batch_init(sp2_ctx c, int32_t count, const double* const* F_dev,
+                          const int64_t* n, const int64_t* ldf,
+                          const double* lambda_min, const double* lambda_max,
+                          const int64_t* n_occ, const sp2_options* opt_in) {
   if (!c) return SP2_INVALID_ARG;
   c->err.clear();
   c->inited = false;
   c->ran = false;
+  if (count < 1 || count > 65536 || !F_dev || !n || !ldf || !lambda_min ||
+      !lambda_max || !n_occ)
+    return fail(c, SP2_INVALID_ARG, "count outside [1, 65536] or NULL array",
+                hipSuccess);
   sp2_options opt;
   if (opt_in) {
     opt = *opt_in;
   } else {
     sp2_default_options(&opt);
   }
-  if (opt.max_iter == 0) opt.max_iter = 100;
-  if (!F_dev) return fail(c, SP2_INVALID_ARG, "F_dev is NULL", hipSuccess);
-  if (n <= 0 || n > 65536)
-    return fail(c, SP2_INVALID_ARG, "n must be in [1, 65536]", hipSuccess);
-  if (ldf < n) return fail(c, SP2_INVALID_ARG, "ldf < n", hipSuccess);
-  if (n_occ < 0 || n_occ > n)
-    return fail(c, SP2_INVALID_ARG, "n_occ outside [0, n]", hipSuccess);
-  if (!isfinite(lambda_min) || !isfinite(lambda_max) ||
-      !(lambda_max > lambda_min) || !isfinite(lambda_max - lambda_min))
-    return fail(c, SP2_INVALID_ARG,
-                "spectral bounds must be finite with lambda_max > lambda_min",
-                hipSuccess);
-  if (opt.precision < SP2_FP64 || opt.precision > SP2_BF16X3)
-    return fail(c, SP2_INVALID_ARG, "unknown precision", hipSuccess);
-  if (opt.branch != SP2_BRANCH_NEAREST && opt.branch != SP2_BRANCH_LITERAL)
-    return fail(c, SP2_INVALID_ARG, "unknown branch rule", hipSuccess);
-  if (!(opt.trunc_tau >= 0.0) || !isfinite(opt.trunc_tau))
-    return fail(c, SP2_INVALID_ARG, "trunc_tau must be finite and >= 0",
-                hipSuccess);
-  if (opt.max_iter < 1 || opt.max_iter > SP2_MAX_ITER_LIMIT)
-    return fail(c, SP2_INVALID_ARG, "max_iter outside [1, SP2_MAX_ITER_LIMIT]",
-                hipSuccess);
-  int tile = opt.tile ? opt.tile : default_tile(opt.precision, n);
-  if (!sp2::square_tile_supported(opt.precision, tile))
-    return fail(c, SP2_INVALID_ARG, "unsupported tile", hipSuccess);
-
-  SP2_HIP(c, hipSetDevice(c->device));
-  const int64_t np = ((n + tile - 1) / tile) * tile;
-  const bool fp64 = (opt.precision == SP2_FP64);
-  const size_t xb = static_cast<size_t>(np) * np * (fp64 ? 8 : 4);
-  if (xb > c->x_bytes) {
-    SP2_HIP(c, hipStreamSynchronize(c->stream));
-    for (void*& p : c->X) {
-      if (p) (void)hipFree(p);
-      p = nullptr;
+  sp2_status st = validate_options(c, opt);
+  if (st != SP2_OK) return st;
+  std::vector<HostInst> hi(count);
+  for (int b = 0; b < count; ++b) {
+    st = validate_instance(c, F_dev[b], n[b], ldf[b], lambda_min[b],
+                           lambda_max[b], n_occ[b]);
+    if (st != SP2_OK) {
+      c->err += " (instance " + std::to_string(b) + ")";
+      return st;
     }
-    c->x_bytes = 0;
-    for (void*& p : c->X) SP2_HIP(c, hipMalloc(&p, xb));
-    c->x_bytes = xb;
+    hi[b].F = F_dev[b];
+    hi[b].n = n[b];
+    hi[b].ldf = ldf[b];
+    hi[b].lmin = lambda_min[b];
+    hi[b].lmax = lambda_max[b];
+    hi[b].n_occ = n_occ[b];
   }
-  const int nt = static_cast<int>(np / tile);
-  std::vector<int2> tl = build_tile_list(nt);
-  const size_t f0_blocks = static_cast<size_t>(np / kF0Rows);
-  const size_t need_part = std::max(tl.size(), f0_blocks);
-  if (need_part > c->part_count) {
-    SP2_HIP(c, hipStreamSynchronize(c->stream));
-    if (c->part) (void)hipFree(c->part);
-    c->part = nullptr;
-    c->part_count = 0;
-    SP2_HIP(c, hipMalloc(&c->part, need_part * 3 * sizeof(double)));
-    c->part_count = need_part;
-  }
-  if (tl.size() > c->tiles_cap) {
-    SP2_HIP(c, hipStreamSynchronize(c->stream));
-    if (c->tiles) (void)hipFree(c->tiles);
-    c->tiles = nullptr;
-    c->tiles_cap = 0;
-    SP2_HIP(c, hipMalloc(&c->tiles, tl.size() * sizeof(int2)));
-    c->tiles_cap = tl.size();
-  }
-  SP2_HIP(c, hipMemcpyAsync(c->tiles, tl.data(), tl.size() * sizeof(int2),
-                            hipMemcpyHostToDevice, c->stream));
-  SP2_HIP(c, hipStreamSynchronize(c->stream));
-  c->ntiles = static_cast<int>(tl.size());
-  c->per_xcd = (c->ntiles + 7) / 8;
-  c->F = F_dev;
-  c->n = n;
-  c->ldf = ldf;
-  c->n_occ = n_occ;
-  c->np = np;
-  c->lmin = lambda_min;
-  c->lmax = lambda_max;
+  SP2_HIP(c, hipSetDevice(c->device));
   c->opt = opt;
-  c->tile = tile;
-  c->fp64_store = fp64;
+  c->fp64_store = (opt.precision == SP2_FP64);
+  c->hi = std::move(hi);
+  st = setup(c);
+  if (st != SP2_OK) return st;
   c->inited = true;
   return SP2_OK;
 }
 
-sp2_status sp2_run(sp2_ctx c) {
+sp2_status sp2_init_dense(sp2_ctx c, const double* F_dev, int64_t n,
+                          int64_t ldf, double lambda_min, double lambda_max,
+                          int64_t n_occ, const sp2_options* opt) {
+  return sp2_batch_init(c, 1, &F_dev, &n, &ldf, &lambda_min, &lambda_max,
+                        &n_occ, opt);
+}
+
+sp2_status sp2_batch_run(sp2_ctx c) {
   if (!c) return SP2_INVALID_ARG;
-  if (!c->inited) return fail(c, SP2_BAD_STATE, "sp2_run before init", hipSuccess);
+  if (!c->inited) return fail(c, SP2_BAD_STATE, "run before init", hipSuccess);
   c->err.clear();
   c->ran = false;
-  SP2_HIP(c, hipSetDevice(c->device));
-  hipStream_t s = c->stream;
-  const int n = static_cast<int>(c->n), np = static_cast<int>(c->np);
+  return run_batch(c);
+}
 
-  c->trivial = (c->n_occ == 0 || c->n_occ == c->n);
-  SP2_HIP(c, hipEventRecord(c->ev_start, s));
-  SP2_HIP(c, sp2::launch_state_reset(c->st, s));
-  if (c->trivial) {
-    SP2_HIP(c, sp2::launch_fill(c->X[0], c->fp64_store, n, np,
-                                c->n_occ == c->n ? 1 : 0, s));
-    SP2_HIP(c, hipEventRecord(c->ev_stop, s));
-    SP2_HIP(c, hipEventSynchronize(c->ev_stop));
-    float ms = 0.f;
-    SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
-    memset(&c->host_state, 0, sizeof(DevState));
-    c->host_state.p[0] = -1;
-    c->result_buf = 0;
-    c->n_iter = 0;
-    c->n_squares = 0;
-    c->run_ms = ms;
-    c->last = SP2_OK;
-    c->ran = true;
-    return SP2_OK;
-  }
+sp2_status sp2_run(sp2_ctx c) {
+  sp2_status st = sp2_batch_run(c);
+  if (st != SP2_OK) return st;
+  return static_cast<sp2_status>(c->host_state[0].status);
+}
 
-  c->mirror->done = 0;
-  c->mirror->status = 0;
-  c->mirror->n = 0;
-  c->mirror->squares = 0;
-  __atomic_thread_fence(__ATOMIC_SEQ_CST);
+sp2_status sp2_batch_get(sp2_ctx c, int32_t idx, void* D_dev, int64_t ldd,
+                         int32_t as_fp64, int32_t* n_iter, int32_t* n_squares,
+                         int32_t* status) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran) return fail(c, SP2_BAD_STATE, "no completed run", hipSuccess);
+  if (idx < 0 || idx >= static_cast<int32_t>(c->hi.size()))
+    return fail(c, SP2_INVALID_ARG, "instance index out of range", hipSuccess);
+  const DevState& h = c->host_state[idx];
+  if (n_iter) *n_iter = h.n;
+  if (n_squares) *n_squares = c->hi[idx].trivial ? 0 : h.squares;
+  if (status) *status = h.status;
+  if (D_dev) return copy_density(c, idx, D_dev, ldd, as_fp64);
+  return SP2_OK;
+}
 
-  sp2::StopParams prm;
-  prm.n_occ = static_cast<double>(c->n_occ);
-  prm.n = static_cast<double>(c->n);
-  prm.branch = c->opt.branch;
-  prm.max_iter = c->opt.max_iter;
-
-  SP2_HIP(c, sp2::launch_f0(c->F, c->ldf, n, np, c->lmax, c->lmax - c->lmin,
-                            c->opt.trunc_tau, c->X[0], c->fp64_store, c->part,
-                            kF0Rows, s));
-  SP2_HIP(c, sp2::launch_finalize(c->part, np / kF0Rows, c->st, c->mirror, 0,
-                                  prm, s));
-  SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
-
-  const bool timing = c->opt.kernel_timing != 0;
-  if (timing && c->ev_sq.empty()) {
-    c->ev_sq.assign(2 * (SP2_MAX_ITER_LIMIT + 1), nullptr);
-    for (hipEvent_t& e : c->ev_sq) SP2_HIP(c, hipEventCreate(&e));
-  }
-  c->timed = false;
-  c->square_ms.clear();
-
-  sp2::SquareArgs a;
-  a.ld = np;
-  a.tiles = c->tiles;
-  a.ntiles = c->ntiles;
-  a.per_xcd = c->per_xcd;
-  a.st = c->st;
-  a.part = c->part;
-  a.tau = c->opt.trunc_tau;
-  for (int i = 1; i <= c->opt.max_iter; ++i) {
-    if (i > kLookahead) {
-      SP2_HIP(c, hipEventSynchronize(c->ev_ring[(i - kLookahead) % kRing]));
-      if (__atomic_load_n(&c->mirror->done, __ATOMIC_ACQUIRE)) break;
-    }
-    a.X = c->X[(i - 1) & 1];
-    a.Y = c->X[i & 1];
-    a.iter = i;
-    if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i], s));
-    hipError_t e;
-    switch (c->opt.precision) {
-      case SP2_FP64: e = sp2::launch_square_f64(a, c->tile, s); break;
-      case SP2_FP32: e = sp2::launch_square_f32(a, c->tile, s); break;
-      default: e = sp2::launch_square_bf16x3(a, c->tile, s); break;
-    }
-    SP2_HIP(c, e);
-    if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i + 1], s));
-    SP2_HIP(c, sp2::launch_finalize(c->part, c->ntiles, c->st, c->mirror, i,
-                                    prm, s));
-    SP2_HIP(c, hipEventRecord(c->ev_ring[i % kRing], s));
-  }
-  SP2_HIP(c, hipEventRecord(c->ev_stop, s));
-  SP2_HIP(c, hipEventSynchronize(c->ev_stop));
-  float ms = 0.f;
-  SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
-  SP2_HIP(c, hipMemcpyAsync(&c->host_state, c->st, sizeof(DevState),
-                            hipMemcpyDeviceToHost, s));
-  SP2_HIP(c, hipStreamSynchronize(s));
-  const DevState& h = c->host_state;
-  if (!h.done)
-    return fail(c, SP2_BAD_STATE, "run ended without an outcome", hipSuccess);
-  c->run_ms = ms;
-  c->n_iter = h.n;
-  c->n_squares = h.squares;
-  c->result_buf = h.n & 1;
-  c->last = static_cast<sp2_status>(h.status);
-  if (timing) {
-    for (int i = 1; i <= h.squares; ++i) {
-      float t = 0.f;
-      SP2_HIP(c, hipEventElapsedTime(&t, c->ev_sq[2 * i], c->ev_sq[2 * i + 1]));
-      c->square_ms.push_back(t);
-    }
-    c->timed = true;
-  }
-  c->ran = true;
-  return c->last;
+sp2_status sp2_batch_get_history(sp2_ctx c, int32_t idx, int32_t cap,
+                                 int32_t* len, double* v, double* t1,
+                                 double* t2, int8_t* p, double* r) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran) return SP2_BAD_STATE;
+  if (cap < 0 || idx < 0 || idx >= static_cast<int32_t>(c->hi.size()))
+    return SP2_INVALID_ARG;
+  fill_history(c, idx, cap, len, v, t1, t2, p, r);
+  return SP2_OK;
 }
 
 sp2_status sp2_get_density(sp2_ctx c, void* D_dev, int64_t ldd,
                            int32_t as_fp64) {
   if (!c) return SP2_INVALID_ARG;
   if (!c->ran) return fail(c, SP2_BAD_STATE, "no completed run", hipSuccess);
-  if (!D_dev || ldd < c->n)
-    return fail(c, SP2_INVALID_ARG, "D_dev NULL or ldd < n", hipSuccess);
-  SP2_HIP(c, hipSetDevice(c->device));
-  SP2_HIP(c, sp2::launch_copy_out(c->X[c->result_buf], c->fp64_store,
-                                  static_cast<int>(c->n),
-                                  static_cast<int>(c->np), D_dev, ldd,
-                                  as_fp64 != 0, c->stream));
-  SP2_HIP(c, hipStreamSynchronize(c->stream));
-  return SP2_OK;
+  return copy_density(c, 0, D_dev, ldd, as_fp64);
 }
 
 sp2_status sp2_get_info(sp2_ctx c, int32_t* n_iter, int32_t* n_squares,
                         double* run_ms) {
   if (!c) return SP2_INVALID_ARG;
   if (!c->ran) return SP2_BAD_STATE;
-  if (n_iter) *n_iter = c->n_iter;
-  if (n_squares) *n_squares = c->n_squares;
+  const DevState& h = c->host_state[0];
+  if (n_iter) *n_iter = h.n;
+  if (n_squares) *n_squares = c->hi[0].trivial ? 0 : h.squares;
   if (run_ms) *run_ms = c->run_ms;
+  return SP2_OK;
+}
+
+sp2_status sp2_batch_get_run_time(sp2_ctx c, double* run_ms, int32_t* steps) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran) return SP2_BAD_STATE;
+  if (run_ms) *run_ms = c->run_ms;
+  if (steps) *steps = c->steps;
   return SP2_OK;
 }
 
@@ -449,23 +748,7 @@ sp2_status sp2_get_kernel_times(sp2_ctx c, int32_t cap, int32_t* len,
 
 sp2_status sp2_get_history(sp2_ctx c, int32_t cap, int32_t* len, double* v,
                            double* t1, double* t2, int8_t* p, double* r) {
-  if (!c) return SP2_INVALID_ARG;
-  if (!c->ran) return SP2_BAD_STATE;
-  if (cap < 0) return SP2_INVALID_ARG;
-  const DevState& h = c->host_state;
-  const int nv = c->n_squares;
-  if (len) *len = nv;
-  // Traces exist for X~_0 .. X~_m where m is the last iterate formed.
-  int nt = c->trivial ? 0 : nv + 1;
-  if (!c->trivial && h.status == SP2_DIVERGED && h.n == 0 && nv == 0) nt = 1;
-  for (int k = 0; k < cap; ++k) {
-    if (v) v[k] = k < nv ? h.v[k] : NAN;
-    if (r) r[k] = k < nv ? h.r[k] : NAN;
-    if (t1) t1[k] = k < nt ? h.t1[k] : NAN;
-    if (t2) t2[k] = k < nt ? h.t2[k] : NAN;
-    if (p) p[k] = k < nt ? (k == 0 ? -1 : h.p[k]) : -1;
-  }
-  return SP2_OK;
+  return sp2_batch_get_history(c, 0, cap, len, v, t1, t2, p, r);
 }
 
 }  // extern "C"

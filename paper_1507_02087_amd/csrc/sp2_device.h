@@ -1,5 +1,10 @@
 // Internal declarations shared by the HIP kernels and the host driver of the
 // SP2 library. Not part of the public ABI (include/sp2.h is).
+//
+// Every run is a batch of independent instances (a single dense run is a
+// batch of one). Each instance has its own iterate buffers, device state,
+// polynomial choices and stop; all instances advance one step per launch
+// sequence, and kernels of an instance that has stopped return at once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,10 +12,12 @@
 
 namespace sp2 {
 
-// Largest number of squares a run may compute (public SP2_MAX_ITER_LIMIT).
+// Largest number of squares one run may compute (public SP2_MAX_ITER_LIMIT).
 constexpr int kMaxIter = 200;
+// Rows of X_0 per workgroup of the affine-start kernel.
+constexpr int kF0Rows = 8;
 
-// Per-run state kept in device memory. The finalize kernel is its only
+// Per-instance state kept in device memory. The finalize kernel is its only
 // writer during a run; the square kernels read `done` and the polynomial of
 // their step from it. Index conventions follow Alg. 2: p[i] is the
 // polynomial that produced X~_i (p[0] unused), v[k] = ||X~_k - X~_k^2||_F,
@@ -27,14 +34,12 @@ struct DevState {
   double r[kMaxIter + 1];
 };
 
-// Mirror of the outcome fields in host-coherent pinned memory, written by
-// the finalize kernel with system-scope stores so that the host can see the
-// stop without copying device memory.
+// Outcome of the whole batch, in host-coherent pinned memory, written by the
+// finalize kernel with system-scope stores so that the host can see that
+// every instance has stopped without copying device memory.
 struct HostMirror {
-  int32_t done;
-  int32_t status;
-  int32_t n;
-  int32_t squares;
+  int32_t all_done;
+  int32_t pad[3];
 };
 
 // Parameters of the scalar stop/branch logic (Alg. 2).
@@ -45,38 +50,89 @@ struct StopParams {
   int32_t max_iter;  // squares allowed
 };
 
+// One instance as the kernels see it.
+struct Instance {
+  void* X[2];          // iterate buffers (step i reads X[(i-1)&1])
+  const double* F;     // input, FP64, row-major
+  int64_t ldf;
+  int n;               // matrix dimension
+  int ld;              // padded dimension (multiple of the tile edge)
+  int tile0, ntiles;   // range of this instance in the tile table
+  int f0blk0, nf0blk;  // range of its affine-start blocks
+  DevState* st;
+  double lmax, width;  // lambda_max, lambda_max - lambda_min
+  double tau;          // truncation threshold (0 = off)
+  StopParams prm;
+};
+
+// One unit of work of a square launch, given per workgroup by the host:
+// inst/slot = instance and global tile index (slot -1: idle), piece =
+// workspace index of a K-range piece of a tail tile (-1: whole tile),
+// K slices [k0, k1).
+struct WorkItem {
+  int32_t inst;
+  int32_t slot;
+  int32_t piece;
+  int32_t k0;
+  int32_t k1;
+  int32_t pad;
+};
+
+// A tile whose K range was split into pieces; pieces piece0 .. piece0+split-1.
+struct TailItem {
+  int32_t inst;
+  int32_t slot;
+  int32_t piece0;
+  int32_t pad;
+};
+
+// One workgroup of the affine start: instance and first row.
+struct F0Item {
+  int32_t inst;
+  int32_t row0;
+};
+
+// A compiled square-kernel configuration.
+struct KernelConfig {
+  int precision;   // sp2_precision
+  int bm;          // macro tile edge
+  int wm, wn;      // waves along M and N
+  int bk;          // K slice staged per LDS buffer
+  int threads;     // workgroup size
+  int occupancy;   // workgroups per CU the configuration is built for
+};
+
+// Arguments of one square step of one launch group (instances sharing a
+// kernel configuration).
+struct SquareArgs {
+  const Instance* inst;
+  const int2* tiles;          // tile table (I, J), I <= J, per instance
+  const WorkItem* items;      // one per workgroup of the main launch
+  const TailItem* tails;      // one per workgroup of the tail launch
+  void* ws;                   // tail-piece accumulators (FP32 or FP64)
+  int ntail;                  // tail tiles (0: no tail launch)
+  int split;                  // pieces per tail tile
+  int iter;                   // step i: X~_{i-1} -> X~_i
+  double* part;   // 3 doubles per tile (global slot): ||X - S||_F^2, Tr, sum x^2
+};
+
 // Host-side launchers (implemented in the .hip files).
-hipError_t launch_state_reset(DevState* st, hipStream_t s);
-hipError_t launch_f0(const double* F, int64_t ldf, int n, int np, double lmax,
-                     double width, double tau, void* X0, bool fp64_store,
-                     double* part, int rows_per_block, hipStream_t s);
-hipError_t launch_finalize(const double* part, int count, DevState* st,
-                           HostMirror* mirror, int iter, StopParams prm,
+hipError_t launch_state_reset(DevState* st, int count, int32_t* ndone,
+                              hipStream_t s);
+hipError_t launch_f0(const Instance* inst, const F0Item* items, int nitems,
+                     bool fp64_store, double* part_f0, hipStream_t s);
+hipError_t launch_finalize(const Instance* inst, int count,
+                           const double* part, const double* part_f0,
+                           int32_t* ndone, HostMirror* mirror, int iter,
                            hipStream_t s);
-hipError_t launch_fill(void* X, bool fp64_store, int n, int np, int identity,
-                       hipStream_t s);
 hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
                            void* D, int64_t ldd, bool out_fp64,
                            hipStream_t s);
 
-// One symmetric square step: reads X~_{iter-1} from X, writes X~_iter to Y
-// (upper tiles and their mirrors), one FP64 partial triple per tile.
-struct SquareArgs {
-  const void* X;
-  void* Y;
-  int ld;              // padded dimension (multiple of the tile edge)
-  const int2* tiles;   // upper-triangle tile coordinates, XCD-grouped order
-  int ntiles;
-  int per_xcd;         // ceil(ntiles / 8)
-  const DevState* st;
-  int iter;
-  double* part;        // 3 doubles per tile: ||X - S||_F^2, Tr, ||X_new||_F^2
-  double tau;
-};
-
-hipError_t launch_square_f64(const SquareArgs& a, int tile, hipStream_t s);
-hipError_t launch_square_f32(const SquareArgs& a, int tile, hipStream_t s);
-hipError_t launch_square_bf16x3(const SquareArgs& a, int tile, hipStream_t s);
-bool square_tile_supported(int precision, int tile);
+int kernel_config_count();
+const KernelConfig* kernel_config(int id);   // id in [0, count)
+// Launches the main square kernel of configuration `id` with `grid`
+// workgroups, then (if a.ntail > 0) the tail reduction kernel.
+hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s);
 
 }  // namespace sp2

@@ -7,23 +7,25 @@
 // transposed. The epilogue of each tile fuses the rest of the step:
 //   d = X_old - S            (FP64)  -> sum d^2 = ||X~_{i-1} - X~_{i-1}^2||_F^2
 //   X_new = S or 2 X_old - S  (Alg. 2, polynomial p_i read from device state)
-//   |X_new| < tau -> 0        (truncation E_i, sec. 5)
+//   |X_new| < tau -> 0        (truncation E_i, sec. 5; compared in FP64)
 //   Tr X_new and sum X_new^2  (FP64; traces for the next polynomial choice)
 // Off-diagonal tiles count twice in the sums. In diagonal tiles only the
 // upper triangle (row <= col) is used and mirrored, so every iterate is
 // exactly symmetric.
 //
-// Each workgroup (4 waves) owns a BM x BM macro tile; the K loop stages
-// BM x BK slices of the two row panels through double-buffered LDS with a
-// register prefetch of the next slice. Within a wave the k index assigned to
-// (MFMA substep, lane group) is permuted so that every lane reads a
-// contiguous run of k from LDS; both operands use the same permutation, so
-// the sum over k is unchanged.
+// Work decomposition: the host gives every workgroup a WorkItem: a whole
+// tile, one K-range piece of a tail tile, or nothing. Tail tiles are the
+// tiles of an incomplete last round of workgroups; splitting each into
+// several K pieces lets that round finish in a fraction of a tile's time.
+// A piece stores its FP32/FP64 accumulators to a workspace in register order
+// and a second kernel sums the pieces of each tail tile in a fixed order and
+// runs the same epilogue (deterministic; no atomics).
 //
-// Workgroup -> tile mapping is XCD aware: dispatch places workgroup b on XCD
-// b mod 8, and XCD x processes the contiguous chunk x of a tile list ordered
-// by groups of neighbouring tiles, which keeps the row panels those tiles
-// share resident in that XCD's L2.
+// Each workgroup stages BM x BK slices of the two row panels through
+// double-buffered LDS with a register prefetch of the next slice. The k index
+// assigned to (MFMA substep, lane group) is permuted so that each lane reads
+// contiguous runs of k from LDS; both operands use the same permutation, so
+// the sum over k is unchanged.
 #include "sp2_device.h"
 
 namespace sp2 {
@@ -35,8 +37,6 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kThreads = 256;
-
 struct Sums {
   double v = 0.0, t1 = 0.0, t2 = 0.0;
 };
@@ -47,8 +47,9 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Writes the tile's three partial sums in a fixed order (deterministic).
+template <int THREADS>
 __device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
-  __shared__ double sh[kThreads / 64][3];
+  __shared__ double sh[THREADS / 64][3];
   s.v = wave_sum(s.v);
   s.t1 = wave_sum(s.t1);
   s.t2 = wave_sum(s.t2);
@@ -61,7 +62,7 @@ __device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = sh[0][0], b = sh[0][1], c = sh[0][2];
-    for (int w = 1; w < kThreads / 64; ++w) {
+    for (int w = 1; w < THREADS / 64; ++w) {
       a += sh[w][0];
       b += sh[w][1];
       c += sh[w][2];
@@ -74,7 +75,6 @@ __device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
 
 // The per-element part of the epilogue. w is the multiplicity of the element
 // in the full symmetric matrix (2 off the diagonal, 1 on it).
-// The truncation test compares the stored value in FP64.
 template <typename T>
 __device__ __forceinline__ T epilogue_elem(T s, T xo, int p, double tau,
                                            double w, bool on_diag, Sums& acc) {
@@ -91,140 +91,315 @@ __device__ __forceinline__ T epilogue_elem(T s, T xo, int p, double tau,
   return xn;
 }
 
-__device__ __forceinline__ int tile_slot(int per_xcd) {
-  return static_cast<int>(blockIdx.x % 8u) * per_xcd +
-         static_cast<int>(blockIdx.x / 8u);
+// Applies the epilogue to one accumulator value at tile-local (lr, lc).
+template <typename T>
+__device__ __forceinline__ void epilogue_at(const T* __restrict__ X,
+                                            T* __restrict__ Y, int ld, int I,
+                                            int J, int BM, int lr, int lc,
+                                            T s, int p, double tau,
+                                            Sums& sums) {
+  const int gr = I * BM + lr, gc = J * BM + lc;
+  const size_t idx = static_cast<size_t>(gr) * ld + gc;
+  if (I != J) {
+    const T xn = epilogue_elem<T>(s, X[idx], p, tau, 2.0, false, sums);
+    Y[idx] = xn;
+    Y[static_cast<size_t>(gc) * ld + gr] = xn;
+  } else if (gr <= gc) {
+    const bool on = (gr == gc);
+    const T xn = epilogue_elem<T>(s, X[idx], p, tau, on ? 1.0 : 2.0, on, sums);
+    Y[idx] = xn;
+    if (!on) Y[static_cast<size_t>(gc) * ld + gr] = xn;
+  }
 }
 
-// ---------------------------------------------------------------- FP32
-// 128 x 128 macro tile, BK = 32, waves in 2 x 2, each wave 64 x 64 made of
-// 2 x 2 blocks of v_mfma_f32_32x32x2_f32. Lane l of a 32x32 block supplies
-// A[row = l % 32][kk = l / 32] and B[kk = l / 32][col = l % 32]; accumulator
-// register j of lane l holds row 8 (j/4) + 4 (l/32) + j%4, column l % 32.
-namespace f32 {
-constexpr int BM = 128, BK = 32, LDK = BK + 4;
-}
-
-__global__ __launch_bounds__(kThreads) void square_f32_kernel(SquareArgs a) {
-  using namespace f32;
-  __shared__ __attribute__((aligned(16))) float As[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BM][LDK];
-  if (a.st->done) return;
-  const int slot = tile_slot(a.per_xcd);
-  if (slot >= a.ntiles) return;
-  const int2 tt = a.tiles[slot];
-  const int I = tt.x, J = tt.y;
-  const int p = a.st->p[a.iter];
-  const int ld = a.ld;
-  const float* __restrict__ X = static_cast<const float*>(a.X);
-  float* __restrict__ Y = static_cast<float*>(a.Y);
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int r = lane & 31, h = lane >> 5;
-  const float* Ap = X + static_cast<size_t>(I * BM) * ld;
-  const float* Bp = X + static_cast<size_t>(J * BM) * ld;
-  const int lr = tid >> 3, lc = (tid & 7) * 4;
-
-  floatx4 ra[4], rb[4];
-  auto gload = [&](int k0) {
+// Global -> register staging of a BM x BK slice of two row panels, in
+// 16-byte chunks (CH elements each), spread over THREADS threads.
+template <typename T, int BM, int BK, int THREADS>
+struct Stage {
+  static constexpr int CH = 16 / sizeof(T);
+  static constexpr int CPR = BK / CH;                 // chunks per row
+  static constexpr int NCH = BM * CPR / THREADS;      // chunks per thread
+  static_assert(BM * CPR % THREADS == 0, "stage size");
+  typedef T vec __attribute__((ext_vector_type(CH)));
+  vec a[NCH], b[NCH];
+  __device__ __forceinline__ static int row(int tid, int q) {
+    return (tid + q * THREADS) / CPR;
+  }
+  __device__ __forceinline__ static int col(int tid, int q) {
+    return ((tid + q * THREADS) % CPR) * CH;
+  }
+  __device__ __forceinline__ void load(const T* Ap, const T* Bp, int ld,
+                                       int k0, int tid) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = *reinterpret_cast<const floatx4*>(
-          Ap + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
-      rb[q] = *reinterpret_cast<const floatx4*>(
-          Bp + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
+    for (int q = 0; q < NCH; ++q) {
+      const size_t off =
+          static_cast<size_t>(row(tid, q)) * ld + k0 + col(tid, q);
+      a[q] = *reinterpret_cast<const vec*>(Ap + off);
+      b[q] = *reinterpret_cast<const vec*>(Bp + off);
     }
+  }
+};
+
+// What one workgroup needs to know about its step, built at kernel start.
+template <typename T>
+struct StepCtx {
+  const T* X;     // X~_{i-1}
+  T* Y;           // X~_i
+  int ld;
+  int2 tile;      // (I, J)
+  int p;          // polynomial of step i
+  double tau;
+};
+
+template <typename T>
+__device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
+                                               const Instance& in, int slot) {
+  StepCtx<T> c;
+  c.X = static_cast<const T*>(in.X[(a.iter - 1) & 1]);
+  c.Y = static_cast<T*>(in.X[a.iter & 1]);
+  c.ld = in.ld;
+  c.tile = a.tiles[slot];
+  c.p = in.st->p[a.iter];
+  c.tau = in.tau;
+  return c;
+}
+
+// ============================================================== FP64
+// v_mfma_f64_16x16x4_f64: lane l supplies A[row = l % 16][kk = l / 16] and
+// B[kk = l / 16][col = l % 16]; accumulator register j of lane l holds row
+// l / 16 + 4 j, column l % 16 (checked with an on-device layout probe).
+template <int BM_, int WM_, int WN_, int BK_>
+struct CfgF64 {
+  using T = double;
+  static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BM / WN;
+  static constexpr int MB = TM / 16, NB = TN / 16;
+  static constexpr int KS = BK / 4;     // MFMA substeps per K slice
+  static constexpr int LDK = BK + 2;    // LDS row stride (doubles)
+  struct Acc {
+    doublex4 c[MB][NB];
   };
+};
+
+template <class C>
+__device__ __forceinline__ void acc_zero(typename C::Acc& acc) {
+#pragma unroll
+  for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < C::NB; ++n)
+#pragma unroll
+      for (int j = 0; j < static_cast<int>(sizeof(acc.c[0][0]) /
+                                          sizeof(acc.c[0][0][0]));
+           ++j)
+        acc.c[m][n][j] = 0;
+}
+
+template <class C>
+__device__ __forceinline__ void mainloop_f64(const StepCtx<double>& sc,
+                                             const WorkItem& w,
+                                             typename C::Acc& acc) {
+  using T = double;
+  __shared__ __attribute__((aligned(16))) T As[2][C::BM][C::LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][C::BM][C::LDK];
+  const int2 tt = sc.tile;
+  const int ld = sc.ld;
+  const T* X = sc.X;
+  const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
+  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  const int r = lane & 15, g = lane >> 4;
+  using St = Stage<T, C::BM, C::BK, C::THREADS>;
+  St st;
   auto sstore = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<floatx4*>(&As[b][lr + 32 * q][lc]) = ra[q];
-      *reinterpret_cast<floatx4*>(&Bs[b][lr + 32 * q][lc]) = rb[q];
+    for (int q = 0; q < St::NCH; ++q) {
+      const int rr = St::row(tid, q), cc = St::col(tid, q);
+      *reinterpret_cast<typename St::vec*>(&As[b][rr][cc]) = st.a[q];
+      *reinterpret_cast<typename St::vec*>(&Bs[b][rr][cc]) = st.b[q];
     }
   };
-
-  floatx16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
-
-  const int nk = ld / BK;
-  gload(0);
+  acc_zero<C>(acc);
+  st.load(Ap, Bp, ld, w.k0 * C::BK, tid);
   sstore(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int b = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    floatx4 af[2][4], bfr[2][4];
+  for (int kt = w.k0; kt < w.k1; ++kt) {
+    const int b = (kt - w.k0) & 1;
+    if (kt + 1 < w.k1) st.load(Ap, Bp, ld, (kt + 1) * C::BK, tid);
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int s2 = 0; s2 < C::KS; s2 += 2) {
+      double2 af[C::MB], bf[C::NB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        af[m][q] = *reinterpret_cast<const floatx4*>(
-            &As[b][wm + m * 32 + r][h * 16 + q * 4]);
-        bfr[m][q] = *reinterpret_cast<const floatx4*>(
-            &Bs[b][wn + m * 32 + r][h * 16 + q * 4]);
-      }
+      for (int m = 0; m < C::MB; ++m)
+        af[m] = *reinterpret_cast<const double2*>(
+            &As[b][wm + m * 16 + r][g * C::KS + s2]);
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
+      for (int n = 0; n < C::NB; ++n)
+        bf[n] = *reinterpret_cast<const double2*>(
+            &Bs[b][wn + n * 16 + r][g * C::KS + s2]);
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-              af[m][s >> 2][s & 3], bfr[n][s >> 2][s & 3], acc[m][n], 0, 0, 0);
-    if (kt + 1 < nk) sstore(b ^ 1);
+        for (int n = 0; n < C::NB; ++n)
+          acc.c[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              af[m].x, bf[n].x, acc.c[m][n], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n)
+          acc.c[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              af[m].y, bf[n].y, acc.c[m][n], 0, 0, 0);
+    }
+    if (kt + 1 < w.k1) sstore(b ^ 1);
     __syncthreads();
   }
+}
 
-  // Epilogue.
+template <class C>
+__device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
+                                             double* part, int slot,
+                                             const typename C::Acc& acc) {
+  using T = double;
+  const int2 tt = sc.tile;
+  const int p = sc.p;
+  const T* X = sc.X;
+  T* Y = sc.Y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   Sums sums;
-  const double tau = a.tau;
-  const bool diag_tile = (I == J);
 #pragma unroll
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      const int gc = J * BM + wn + n * 32 + r;
+    for (int n = 0; n < C::NB; ++n)
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int gr0 = I * BM + wm + m * 32 + 8 * jj + 4 * h;
-        floatx4 out;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gr = gr0 + e;
-          const size_t idx = static_cast<size_t>(gr) * ld + gc;
-          const float s = acc[m][n][jj * 4 + e];
-          if (!diag_tile) {
-            out[e] = epilogue_elem<float>(s, X[idx], p, tau, 2.0, false, sums);
-            Y[idx] = out[e];
-          } else if (gr <= gc) {
-            const bool on = (gr == gc);
-            const float xn = epilogue_elem<float>(s, X[idx], p, tau,
-                                                  on ? 1.0 : 2.0, on, sums);
-            Y[idx] = xn;
-            if (!on) Y[static_cast<size_t>(gc) * ld + gr] = xn;
-          }
-        }
-        if (!diag_tile)
-          *reinterpret_cast<floatx4*>(Y + static_cast<size_t>(gc) * ld + gr0) =
-              out;
-      }
-    }
-  store_partials(sums, a.part, slot);
+      for (int j = 0; j < 4; ++j)
+        epilogue_at<T>(X, Y, sc.ld, tt.x, tt.y, C::BM,
+                       wm + m * 16 + (lane >> 4) + 4 * j,
+                       wn + n * 16 + (lane & 15), acc.c[m][n][j], p, sc.tau,
+                       sums);
+  store_partials<C::THREADS>(sums, part, slot);
 }
 
-// ---------------------------------------------------------------- BF16x3
-// Same tiling as FP32 with v_mfma_f32_32x32x16_bf16. Each FP32 element of X
-// is split while it is staged into LDS: H = bf16(x), L = bf16(x - H), both
-// rounded to nearest even; the tile accumulates H H + H L + L H in FP32
-// (the L L term is below FP32 rounding of the result and is dropped).
-// Lane l supplies 8 consecutive k of A[row = l % 32] and B[col = l % 32].
-namespace b3 {
-constexpr int BM = 128, BK = 32, LDK = BK + 8;
+// ============================================================== FP32
+// v_mfma_f32_32x32x2_f32: lane l supplies A[row = l % 32][kk = l / 32] and
+// B[kk = l / 32][col = l % 32]; accumulator register j of lane l holds row
+// 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32.
+template <int BM_, int WM_, int WN_, int BK_>
+struct CfgF32 {
+  using T = float;
+  static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BM / WN;
+  static constexpr int MB = TM / 32, NB = TN / 32;
+  static constexpr int KH = BK / 2;     // k values per lane half per slice
+  static constexpr int LDK = BK + 4;
+  struct Acc {
+    floatx16 c[MB][NB];
+  };
+};
+
+template <class C>
+__device__ __forceinline__ void mainloop_f32(const StepCtx<float>& sc,
+                                             const WorkItem& w,
+                                             typename C::Acc& acc) {
+  using T = float;
+  __shared__ __attribute__((aligned(16))) T As[2][C::BM][C::LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][C::BM][C::LDK];
+  const int2 tt = sc.tile;
+  const int ld = sc.ld;
+  const T* X = sc.X;
+  const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
+  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  const int r = lane & 31, h = lane >> 5;
+  using St = Stage<T, C::BM, C::BK, C::THREADS>;
+  St st;
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < St::NCH; ++q) {
+      const int rr = St::row(tid, q), cc = St::col(tid, q);
+      *reinterpret_cast<typename St::vec*>(&As[b][rr][cc]) = st.a[q];
+      *reinterpret_cast<typename St::vec*>(&Bs[b][rr][cc]) = st.b[q];
+    }
+  };
+  acc_zero<C>(acc);
+  st.load(Ap, Bp, ld, w.k0 * C::BK, tid);
+  sstore(0);
+  __syncthreads();
+  for (int kt = w.k0; kt < w.k1; ++kt) {
+    const int b = (kt - w.k0) & 1;
+    if (kt + 1 < w.k1) st.load(Ap, Bp, ld, (kt + 1) * C::BK, tid);
+#pragma unroll
+    for (int s4 = 0; s4 < C::KH; s4 += 4) {
+      floatx4 af[C::MB], bf[C::NB];
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+        af[m] = *reinterpret_cast<const floatx4*>(
+            &As[b][wm + m * 32 + r][h * C::KH + s4]);
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n)
+        bf[n] = *reinterpret_cast<const floatx4*>(
+            &Bs[b][wn + n * 32 + r][h * C::KH + s4]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+          for (int n = 0; n < C::NB; ++n)
+            acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                af[m][e], bf[n][e], acc.c[m][n], 0, 0, 0);
+    }
+    if (kt + 1 < w.k1) sstore(b ^ 1);
+    __syncthreads();
+  }
 }
+
+template <class C>
+__device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
+                                             double* part, int slot,
+                                             const typename C::Acc& acc) {
+  using T = float;
+  const int2 tt = sc.tile;
+  const int p = sc.p;
+  const T* X = sc.X;
+  T* Y = sc.Y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  Sums sums;
+#pragma unroll
+  for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < C::NB; ++n)
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        epilogue_at<T>(X, Y, sc.ld, tt.x, tt.y, C::BM,
+                       wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3),
+                       wn + n * 32 + (lane & 31), acc.c[m][n][j], p, sc.tau,
+                       sums);
+  store_partials<C::THREADS>(sums, part, slot);
+}
+
+// ============================================================== BF16x3
+// v_mfma_f32_32x32x16_bf16: lane l supplies 8 consecutive k of
+// A[row = l % 32] and of B[col = l % 32]; the accumulator layout is the FP32
+// 32x32 one. Each FP32 element of X is split while it is staged into LDS:
+// H = bf16(x), L = bf16(x - H), both rounded to nearest even; the tile
+// accumulates H H + H L + L H in FP32 (the L L term is dropped).
+template <int BM_, int WM_, int WN_, int BK_>
+struct CfgB3 {
+  using T = float;
+  static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BM / WN;
+  static constexpr int MB = TM / 32, NB = TN / 32;
+  static constexpr int KH = BK / 2;     // k values per lane half per slice
+  static constexpr int LDK = BK + 8;    // LDS row stride (bf16)
+  struct Acc {
+    floatx16 c[MB][NB];
+  };
+};
 
 __device__ __forceinline__ void split_bf16(floatx4 x, bf16x4& hi, bf16x4& lo) {
 #pragma unroll
@@ -235,283 +410,252 @@ __device__ __forceinline__ void split_bf16(floatx4 x, bf16x4& hi, bf16x4& lo) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void square_bf16x3_kernel(SquareArgs a) {
-  using namespace b3;
-  __shared__ __attribute__((aligned(16))) __bf16 AH[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 AL[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 BH[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 BL[2][BM][LDK];
-  if (a.st->done) return;
-  const int slot = tile_slot(a.per_xcd);
-  if (slot >= a.ntiles) return;
-  const int2 tt = a.tiles[slot];
-  const int I = tt.x, J = tt.y;
-  const int p = a.st->p[a.iter];
-  const int ld = a.ld;
-  const float* __restrict__ X = static_cast<const float*>(a.X);
-  float* __restrict__ Y = static_cast<float*>(a.Y);
-
+template <class C>
+__device__ __forceinline__ void mainloop_b3(const StepCtx<float>& sc,
+                                            const WorkItem& w,
+                                            typename C::Acc& acc) {
+  using T = float;
+  __shared__ __attribute__((aligned(16))) __bf16 AH[2][C::BM][C::LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 AL[2][C::BM][C::LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 BH[2][C::BM][C::LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 BL[2][C::BM][C::LDK];
+  const int2 tt = sc.tile;
+  const int ld = sc.ld;
+  const T* X = sc.X;
+  const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
+  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 31, h = lane >> 5;
-  const float* Ap = X + static_cast<size_t>(I * BM) * ld;
-  const float* Bp = X + static_cast<size_t>(J * BM) * ld;
-  const int lr = tid >> 3, lc = (tid & 7) * 4;
-
-  floatx4 ra[4], rb[4];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = *reinterpret_cast<const floatx4*>(
-          Ap + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
-      rb[q] = *reinterpret_cast<const floatx4*>(
-          Bp + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
-    }
-  };
+  using St = Stage<T, C::BM, C::BK, C::THREADS>;
+  St st;
   auto sstore = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < St::NCH; ++q) {
+      const int rr = St::row(tid, q), cc = St::col(tid, q);
       bf16x4 hi, lo;
-      split_bf16(ra[q], hi, lo);
-      *reinterpret_cast<bf16x4*>(&AH[b][lr + 32 * q][lc]) = hi;
-      *reinterpret_cast<bf16x4*>(&AL[b][lr + 32 * q][lc]) = lo;
-      split_bf16(rb[q], hi, lo);
-      *reinterpret_cast<bf16x4*>(&BH[b][lr + 32 * q][lc]) = hi;
-      *reinterpret_cast<bf16x4*>(&BL[b][lr + 32 * q][lc]) = lo;
+      split_bf16(st.a[q], hi, lo);
+      *reinterpret_cast<bf16x4*>(&AH[b][rr][cc]) = hi;
+      *reinterpret_cast<bf16x4*>(&AL[b][rr][cc]) = lo;
+      split_bf16(st.b[q], hi, lo);
+      *reinterpret_cast<bf16x4*>(&BH[b][rr][cc]) = hi;
+      *reinterpret_cast<bf16x4*>(&BL[b][rr][cc]) = lo;
     }
   };
-
-  floatx16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx16{};
-
-  const int nk = ld / BK;
-  gload(0);
+  acc_zero<C>(acc);
+  st.load(Ap, Bp, ld, w.k0 * C::BK, tid);
   sstore(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int b = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    // 16 consecutive k per lane (two substeps of 8).
-    bf16x8 ah[2][2], al[2][2], bh[2][2], bl[2][2];
+  for (int kt = w.k0; kt < w.k1; ++kt) {
+    const int b = (kt - w.k0) & 1;
+    if (kt + 1 < w.k1) st.load(Ap, Bp, ld, (kt + 1) * C::BK, tid);
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int s8 = 0; s8 < C::KH; s8 += 8) {
+      bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        ah[m][s] = *reinterpret_cast<const bf16x8*>(
-            &AH[b][wm + m * 32 + r][h * 16 + s * 8]);
-        al[m][s] = *reinterpret_cast<const bf16x8*>(
-            &AL[b][wm + m * 32 + r][h * 16 + s * 8]);
-        bh[m][s] = *reinterpret_cast<const bf16x8*>(
-            &BH[b][wn + m * 32 + r][h * 16 + s * 8]);
-        bl[m][s] = *reinterpret_cast<const bf16x8*>(
-            &BL[b][wn + m * 32 + r][h * 16 + s * 8]);
+      for (int m = 0; m < C::MB; ++m) {
+        ah[m] = *reinterpret_cast<const bf16x8*>(
+            &AH[b][wm + m * 32 + r][h * C::KH + s8]);
+        al[m] = *reinterpret_cast<const bf16x8*>(
+            &AL[b][wm + m * 32 + r][h * C::KH + s8]);
       }
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+      for (int n = 0; n < C::NB; ++n) {
+        bh[n] = *reinterpret_cast<const bf16x8*>(
+            &BH[b][wn + n * 32 + r][h * C::KH + s8]);
+        bl[n] = *reinterpret_cast<const bf16x8*>(
+            &BL[b][wn + n * 32 + r][h * C::KH + s8]);
+      }
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m][s], bh[n][s], acc[m][n], 0, 0, 0);
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m][s], bl[n][s], acc[m][n], 0, 0, 0);
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              al[m][s], bh[n][s], acc[m][n], 0, 0, 0);
+        for (int n = 0; n < C::NB; ++n) {
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bh[n], acc.c[m][n], 0, 0, 0);
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bl[n], acc.c[m][n], 0, 0, 0);
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              al[m], bh[n], acc.c[m][n], 0, 0, 0);
         }
-    if (kt + 1 < nk) sstore(b ^ 1);
+    }
+    if (kt + 1 < w.k1) sstore(b ^ 1);
     __syncthreads();
   }
-
-  Sums sums;
-  const double tau = a.tau;
-  const bool diag_tile = (I == J);
-#pragma unroll
-  for (int m = 0; m < 2; ++m)
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      const int gc = J * BM + wn + n * 32 + r;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        const int gr0 = I * BM + wm + m * 32 + 8 * jj + 4 * h;
-        floatx4 out;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int gr = gr0 + e;
-          const size_t idx = static_cast<size_t>(gr) * ld + gc;
-          const float s = acc[m][n][jj * 4 + e];
-          if (!diag_tile) {
-            out[e] = epilogue_elem<float>(s, X[idx], p, tau, 2.0, false, sums);
-            Y[idx] = out[e];
-          } else if (gr <= gc) {
-            const bool on = (gr == gc);
-            const float xn = epilogue_elem<float>(s, X[idx], p, tau,
-                                                  on ? 1.0 : 2.0, on, sums);
-            Y[idx] = xn;
-            if (!on) Y[static_cast<size_t>(gc) * ld + gr] = xn;
-          }
-        }
-        if (!diag_tile)
-          *reinterpret_cast<floatx4*>(Y + static_cast<size_t>(gc) * ld + gr0) =
-              out;
-      }
-    }
-  store_partials(sums, a.part, slot);
 }
 
-// ---------------------------------------------------------------- FP64
-// 128 x 128 macro tile, BK = 16, waves in 2 x 2, each wave 64 x 64 made of
-// 4 x 4 blocks of v_mfma_f64_16x16x4_f64. Lane l of a 16x16 block supplies
-// A[row = l % 16][kk = l / 16] and B[kk = l / 16][col = l % 16]; accumulator
-// register j of lane l holds row 4 (l/16) + j, column l % 16.
-namespace f64 {
-constexpr int BM = 128, BK = 16, LDK = BK + 2;
+// ============================================================== drivers
+// Accumulator registers are stored to the workspace as [reg][thread] so
+// that every store and load is coalesced across the workgroup.
+template <class C>
+__device__ __forceinline__ void ws_store(const typename C::Acc& acc,
+                                         typename C::T* ws) {
+  const int tid = threadIdx.x;
+  constexpr int PER = sizeof(acc.c[0][0]) / sizeof(typename C::T);
+  int k = 0;
+#pragma unroll
+  for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < C::NB; ++n)
+#pragma unroll
+      for (int j = 0; j < PER; ++j, ++k)
+        ws[static_cast<size_t>(k) * C::THREADS + tid] = acc.c[m][n][j];
 }
 
-__global__ __launch_bounds__(kThreads) void square_f64_kernel(SquareArgs a) {
-  using namespace f64;
-  __shared__ __attribute__((aligned(16))) double As[2][BM][LDK];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BM][LDK];
-  if (a.st->done) return;
-  const int slot = tile_slot(a.per_xcd);
-  if (slot >= a.ntiles) return;
-  const int2 tt = a.tiles[slot];
-  const int I = tt.x, J = tt.y;
-  const int p = a.st->p[a.iter];
-  const int ld = a.ld;
-  const double* __restrict__ X = static_cast<const double*>(a.X);
-  double* __restrict__ Y = static_cast<double*>(a.Y);
+template <class C>
+__device__ __forceinline__ void ws_accumulate(typename C::Acc& acc,
+                                              const typename C::T* ws) {
+  const int tid = threadIdx.x;
+  constexpr int PER = sizeof(acc.c[0][0]) / sizeof(typename C::T);
+  int k = 0;
+#pragma unroll
+  for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+    for (int n = 0; n < C::NB; ++n)
+#pragma unroll
+      for (int j = 0; j < PER; ++j, ++k)
+        acc.c[m][n][j] += ws[static_cast<size_t>(k) * C::THREADS + tid];
+}
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int r = lane & 15, g = lane >> 4;
-  const double* Ap = X + static_cast<size_t>(I * BM) * ld;
-  const double* Bp = X + static_cast<size_t>(J * BM) * ld;
-  const int lr = tid >> 3, lc = (tid & 7) * 2;
+template <class C>
+struct Ops;
 
-  double2 ra[4], rb[4];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = *reinterpret_cast<const double2*>(
-          Ap + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
-      rb[q] = *reinterpret_cast<const double2*>(
-          Bp + static_cast<size_t>(lr + 32 * q) * ld + k0 + lc);
-    }
-  };
-  auto sstore = [&](int b) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      *reinterpret_cast<double2*>(&As[b][lr + 32 * q][lc]) = ra[q];
-      *reinterpret_cast<double2*>(&Bs[b][lr + 32 * q][lc]) = rb[q];
-    }
-  };
-
-  doublex4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = doublex4{};
-
-  const int nk = ld / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int b = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-    double af[4][4], bfr[4][4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const double2 a0 = *reinterpret_cast<const double2*>(
-          &As[b][wm + m * 16 + r][g * 4]);
-      const double2 a1 = *reinterpret_cast<const double2*>(
-          &As[b][wm + m * 16 + r][g * 4 + 2]);
-      af[m][0] = a0.x; af[m][1] = a0.y; af[m][2] = a1.x; af[m][3] = a1.y;
-      const double2 b0 = *reinterpret_cast<const double2*>(
-          &Bs[b][wn + m * 16 + r][g * 4]);
-      const double2 b1 = *reinterpret_cast<const double2*>(
-          &Bs[b][wn + m * 16 + r][g * 4 + 2]);
-      bfr[m][0] = b0.x; bfr[m][1] = b0.y; bfr[m][2] = b1.x; bfr[m][3] = b1.y;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-              af[m][s], bfr[n][s], acc[m][n], 0, 0, 0);
-    if (kt + 1 < nk) sstore(b ^ 1);
-    __syncthreads();
+template <int A, int B, int Cc, int D>
+struct Ops<CfgF64<A, B, Cc, D>> {
+  using C = CfgF64<A, B, Cc, D>;
+  using T = typename C::T;
+  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
+                              typename C::Acc& acc) {
+    mainloop_f64<C>(sc, w, acc);
   }
+  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
+                             const typename C::Acc& acc) {
+    epilogue_f64<C>(sc, part, slot, acc);
+  }
+};
 
-  Sums sums;
-  const double tau = a.tau;
-  const bool diag_tile = (I == J);
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const int gc = J * BM + wn + n * 16 + r;
-      const int gr0 = I * BM + wm + m * 16 + 4 * g;
-      double out[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gr = gr0 + e;
-        const size_t idx = static_cast<size_t>(gr) * ld + gc;
-        const double s = acc[m][n][e];
-        if (!diag_tile) {
-          out[e] = epilogue_elem<double>(s, X[idx], p, tau, 2.0, false, sums);
-          Y[idx] = out[e];
-        } else if (gr <= gc) {
-          const bool on = (gr == gc);
-          const double xn = epilogue_elem<double>(s, X[idx], p, tau,
-                                                  on ? 1.0 : 2.0, on, sums);
-          Y[idx] = xn;
-          if (!on) Y[static_cast<size_t>(gc) * ld + gr] = xn;
-        }
-      }
-      if (!diag_tile) {
-        double* dst = Y + static_cast<size_t>(gc) * ld + gr0;
-        *reinterpret_cast<double2*>(dst) = double2{out[0], out[1]};
-        *reinterpret_cast<double2*>(dst + 2) = double2{out[2], out[3]};
-      }
-    }
-  store_partials(sums, a.part, slot);
+template <int A, int B, int Cc, int D>
+struct Ops<CfgF32<A, B, Cc, D>> {
+  using C = CfgF32<A, B, Cc, D>;
+  using T = typename C::T;
+  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
+                              typename C::Acc& acc) {
+    mainloop_f32<C>(sc, w, acc);
+  }
+  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
+                             const typename C::Acc& acc) {
+    epilogue_f32<C>(sc, part, slot, acc);
+  }
+};
+
+template <int A, int B, int Cc, int D>
+struct Ops<CfgB3<A, B, Cc, D>> {
+  using C = CfgB3<A, B, Cc, D>;
+  using T = typename C::T;
+  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
+                              typename C::Acc& acc) {
+    mainloop_b3<C>(sc, w, acc);
+  }
+  // The BF16x3 accumulators have the FP32 32x32 layout.
+  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
+                             const typename C::Acc& acc) {
+    epilogue_f32<C>(sc, part, slot, acc);
+  }
+};
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
+  const WorkItem w = a.items[blockIdx.x];
+  if (w.slot < 0) return;
+  const Instance& in = a.inst[w.inst];
+  if (in.st->done) return;
+  using T = typename C::T;
+  const StepCtx<T> sc = step_ctx<T>(a, in, w.slot);
+  typename C::Acc acc;
+  Ops<C>::main(sc, w, acc);
+  if (w.piece < 0) {
+    Ops<C>::epi(sc, a.part, w.slot, acc);
+  } else {
+    ws_store<C>(acc, static_cast<T*>(a.ws) +
+                         static_cast<size_t>(w.piece) * C::BM * C::BM);
+  }
 }
 
-int grid_of(const SquareArgs& a) { return 8 * a.per_xcd; }
+// Sums the pieces of tail tile blockIdx.x in piece order, then the epilogue.
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
+  const TailItem t = a.tails[blockIdx.x];
+  const Instance& in = a.inst[t.inst];
+  if (in.st->done) return;
+  using T = typename C::T;
+  const StepCtx<T> sc = step_ctx<T>(a, in, t.slot);
+  typename C::Acc acc;
+  acc_zero<C>(acc);
+  const T* ws = static_cast<const T*>(a.ws);
+  for (int j = 0; j < a.split; ++j)
+    ws_accumulate<C>(acc, ws + static_cast<size_t>(t.piece0 + j) *
+                                   C::BM * C::BM);
+  Ops<C>::epi(sc, a.part, t.slot, acc);
+}
+
+// Kernel configurations: macro tile, waves (M x N), K slice.
+using F64_128_2x4 = CfgF64<128, 2, 4, 16>;
+using F64_128_2x2 = CfgF64<128, 2, 2, 16>;
+using F64_64_2x2 = CfgF64<64, 2, 2, 16>;
+using F32_128_2x2 = CfgF32<128, 2, 2, 32>;
+using F32_128_2x4 = CfgF32<128, 2, 4, 32>;
+using F32_256_2x2 = CfgF32<256, 2, 2, 16>;
+using B3_128_2x2 = CfgB3<128, 2, 2, 32>;
+using B3_256_2x2 = CfgB3<256, 2, 2, 16>;
+using B3_256_2x4 = CfgB3<256, 2, 4, 16>;
+
+template <class C>
+hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(square_kernel<C>, dim3(grid), dim3(C::THREADS), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.ntail == 0) return e;
+  hipLaunchKernelGGL(square_tail_kernel<C>, dim3(a.ntail), dim3(C::THREADS), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <class C>
+constexpr KernelConfig describe(int precision, int occupancy) {
+  return KernelConfig{precision, C::BM, C::WM, C::WN, C::BK, C::THREADS,
+                      occupancy};
+}
+
+// Occupancy = workgroups per CU that the configuration's LDS and registers
+// allow; the host uses it to size the split of tail tiles.
+const KernelConfig kConfigs[] = {
+    describe<F64_128_2x4>(0, 1), describe<F64_128_2x2>(0, 1),
+    describe<F64_64_2x2>(0, 2),  describe<F32_128_2x2>(1, 2),
+    describe<F32_128_2x4>(1, 1), describe<F32_256_2x2>(1, 1),
+    describe<B3_128_2x2>(2, 1),  describe<B3_256_2x2>(2, 1),
+    describe<B3_256_2x4>(2, 1),
+};
+constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
 }  // namespace
 
-bool square_tile_supported(int precision, int tile) {
-  (void)precision;
-  return tile == 128;
+int kernel_config_count() { return kNumConfigs; }
+
+const KernelConfig* kernel_config(int id) {
+  return (id >= 0 && id < kNumConfigs) ? &kConfigs[id] : nullptr;
 }
 
-hipError_t launch_square_f64(const SquareArgs& a, int tile, hipStream_t s) {
-  if (tile != f64::BM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(square_f64_kernel, dim3(grid_of(a)), dim3(kThreads), 0, s,
-                     a);
-  return hipGetLastError();
-}
-
-hipError_t launch_square_f32(const SquareArgs& a, int tile, hipStream_t s) {
-  if (tile != f32::BM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(square_f32_kernel, dim3(grid_of(a)), dim3(kThreads), 0, s,
-                     a);
-  return hipGetLastError();
-}
-
-hipError_t launch_square_bf16x3(const SquareArgs& a, int tile, hipStream_t s) {
-  if (tile != b3::BM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(square_bf16x3_kernel, dim3(grid_of(a)), dim3(kThreads), 0,
-                     s, a);
-  return hipGetLastError();
+hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
+  switch (id) {
+    case 0: return launch_cfg<F64_128_2x4>(a, grid, s);
+    case 1: return launch_cfg<F64_128_2x2>(a, grid, s);
+    case 2: return launch_cfg<F64_64_2x2>(a, grid, s);
+    case 3: return launch_cfg<F32_128_2x2>(a, grid, s);
+    case 4: return launch_cfg<F32_128_2x4>(a, grid, s);
+    case 5: return launch_cfg<F32_256_2x2>(a, grid, s);
+    case 6: return launch_cfg<B3_128_2x2>(a, grid, s);
+    case 7: return launch_cfg<B3_256_2x2>(a, grid, s);
+    case 8: return launch_cfg<B3_256_2x4>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace sp2

@@ -45,13 +45,34 @@ def test_status_codes_match_oracle():
         assert lib.sp2_status_string(code).decode() == "SP2_" + name
 
 
-def test_default_options_and_tiles():
+def test_default_options_and_kernel_configs():
     import paper_1507_02087_amd as sp2
     lib = sp2.load_library()
     opt = sp2.Options()
     lib.sp2_default_options(ctypes.byref(opt))
-    assert (opt.precision, opt.branch, opt.trunc_tau, opt.max_iter, opt.tile,
-            opt.kernel_timing) == (0, 0, 0.0, 100, 0, 0)
-    assert sp2.tile_supported("fp64", 128)
-    assert not sp2.tile_supported("fp64", 100)
+    assert (opt.precision, opt.branch, opt.trunc_tau, opt.max_iter, opt.kernel_config,
+            opt.tail_split, opt.kernel_timing) == (0, 0, 0.0, 100, 0, 0, 0)
     assert ctypes.sizeof(sp2.Options) == 32
+    cfgs = sp2.kernel_configs()
+    assert {c["precision"] for c in cfgs} == {"fp64", "fp32", "bf16x3"}
+    for c in cfgs:
+        assert c["tile"] % (16 * c["waves_m"]) == 0 and c["tile"] % (16 * c["waves_n"]) == 0
+    lib = sp2.load_library()
+    assert lib.sp2_kernel_config_info(0, None, None, None, None, None) == sp2.INVALID_ARG
+    assert lib.sp2_kernel_config_info(len(cfgs) + 1, None, None, None, None, None) == sp2.INVALID_ARG
+
+
+def test_library_shares_torch_hip_runtime():
+    """libsp2.so and torch must use one HIP runtime: after loading through
+    the binding, exactly one libamdhip64 is mapped in the process."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_1507_02087_amd as s; "
+            "s.load_library(); import torch; "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') "
+            "if 'libamdhip64' in l}))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
