@@ -174,6 +174,43 @@ sp2_status sp2_get_history(sp2_ctx ctx, int32_t cap, int32_t* len, double* v,
 sp2_status sp2_get_kernel_times(sp2_ctx ctx, int32_t cap, int32_t* len,
                                 float* ms);
 
+/* ---- Block-sparse purification: the iterates are kept in block-sparse
+ * row (BSR) form with 32 x 32 FP32 blocks and truncated by element
+ * magnitude after every step (sec. 5: removal of entries below tau keeps
+ * the iterates of a matrix with decaying entries sparse). ---- */
+
+/* Prepares a block-sparse run. n: dimension; block must be 32; the
+ * nb = ceil(n / 32) block rows are given by row_ptr_dev (nb + 1 entries,
+ * row_ptr[0] = 0, row_ptr[nb] = nnzb) and col_idx_dev (nnzb block columns,
+ * strictly increasing within each row); blocks_dev holds nnzb blocks of
+ * 32 x 32 FP64 values, each row-major. The pattern must be symmetric and
+ * contain every diagonal block; the values must be exactly symmetric
+ * (block (J,I) is the transpose of block (I,J)); entries of the last block
+ * row and column beyond n are ignored. All three arrays are device memory
+ * owned by the caller; blocks_dev must stay valid until sp2_run returns
+ * (row_ptr/col_idx are copied during this call). opt->precision must be
+ * SP2_FP32 (NULL opt: SP2_FP32 defaults); trunc_tau is the element
+ * threshold. The library keeps room for up to min(nb^2, 16 nnzb + 64 nb)
+ * blocks per iterate; sp2_run reports SP2_OUT_OF_MEMORY when the fill
+ * exceeds it. Errors: SP2_INVALID_ARG (the message names the failed check),
+ * SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. After this call sp2_run, sp2_get_info,
+ * sp2_get_history and sp2_get_density (dense n x n expansion) apply. */
+sp2_status sp2_init_bsr(sp2_ctx ctx, int64_t n, int32_t block, int64_t nnzb,
+                        const int32_t* row_ptr_dev, const int32_t* col_idx_dev,
+                        const double* blocks_dev, double lambda_min,
+                        double lambda_max, int64_t n_occ,
+                        const sp2_options* opt);
+
+/* Number of nonzero blocks of the returned block-sparse iterate. */
+sp2_status sp2_get_bsr_nnzb(sp2_ctx ctx, int64_t* nnzb);
+
+/* Copies the returned block-sparse iterate (its nonzero blocks only) to
+ * caller device arrays: row_ptr_dev (nb + 1), col_idx_dev (nnzb, sorted per
+ * row) and blocks_dev (nnzb blocks of 32 x 32, FP64 when as_fp64 != 0 else
+ * FP32), nnzb as reported by sp2_get_bsr_nnzb. */
+sp2_status sp2_get_bsr(sp2_ctx ctx, int32_t* row_ptr_dev, int32_t* col_idx_dev,
+                       void* blocks_dev, int32_t as_fp64);
+
 /* ---- Batched purification: many independent matrices, one launch
  * sequence per step, each instance with its own polynomial choices and its
  * own stop (Alg. 2 applied to every instance). A dense run (sp2_init_dense)

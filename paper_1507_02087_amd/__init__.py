@@ -40,6 +40,12 @@ SIGNATURES = {
                                    _c.c_void_p, _c.c_void_p]),
     "sp2_get_kernel_times": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
                                         _c.c_void_p]),
+    "sp2_init_bsr": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int64,
+                                _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
+                                _c.c_double, _c.c_int64, _c.c_void_p]),
+    "sp2_get_bsr_nnzb": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
+    "sp2_get_bsr": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                               _c.c_int32]),
     "sp2_batch_init": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]),
@@ -245,6 +251,54 @@ class Context:
         m = ln.value
         return dict(v=v[:m].tolist(), r=r[:m].tolist(), t1=t1[:m + 1].tolist(),
                     t2=t2[:m + 1].tolist(), p=p[:m + 1].astype(int).tolist())
+
+
+class BsrContext(Context):
+    """A context running the block-sparse (32 x 32 blocks, FP32) path."""
+
+    def init_bsr(self, n: int, row_ptr, col_idx, blocks, lambda_min: float,
+                 lambda_max: float, n_occ: int, trunc_tau: float = 0.0,
+                 branch: str = "nearest", max_iter: int = 100,
+                 kernel_timing: bool = False):
+        """row_ptr/col_idx: int32 CUDA tensors; blocks: float64 CUDA tensor of
+        shape (nnzb, 32, 32)."""
+        import torch
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr and col_idx must be int32")
+        if blocks.dtype != torch.float64 or not blocks.is_contiguous():
+            raise TypeError("blocks must be a contiguous float64 tensor")
+        if not (row_ptr.is_cuda and col_idx.is_cuda and blocks.is_cuda):
+            raise TypeError("arrays must be CUDA tensors")
+        opt = Options(PRECISIONS["fp32"], BRANCHES[branch], float(trunc_tau),
+                      int(max_iter), 0, 0, 1 if kernel_timing else 0)
+        self._keep = (row_ptr, col_idx, blocks)
+        st = self._lib.sp2_init_bsr(self._h, int(n), 32, int(col_idx.numel()),
+                                    ctypes.c_void_p(row_ptr.data_ptr()),
+                                    ctypes.c_void_p(col_idx.data_ptr()),
+                                    ctypes.c_void_p(blocks.data_ptr()),
+                                    float(lambda_min), float(lambda_max), int(n_occ),
+                                    ctypes.byref(opt))
+        self._check(st, "sp2_init_bsr")
+        self._n = int(n)
+        self._prec = "fp32"
+
+    def get_bsr(self, as_fp64: bool = True):
+        """(row_ptr, col_idx, blocks) of the returned iterate's nonzero blocks."""
+        import torch
+        nnzb = ctypes.c_int64()
+        self._check(self._lib.sp2_get_bsr_nnzb(self._h, ctypes.byref(nnzb)),
+                    "sp2_get_bsr_nnzb")
+        nb = (self._n + 31) // 32
+        dev = f"cuda:{self.device}"
+        rp = torch.empty(nb + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(max(1, nnzb.value), dtype=torch.int32, device=dev)
+        bl = torch.empty((max(1, nnzb.value), 32, 32),
+                         dtype=torch.float64 if as_fp64 else torch.float32, device=dev)
+        self._check(self._lib.sp2_get_bsr(self._h, ctypes.c_void_p(rp.data_ptr()),
+                                          ctypes.c_void_p(ci.data_ptr()),
+                                          ctypes.c_void_p(bl.data_ptr()),
+                                          1 if as_fp64 else 0), "sp2_get_bsr")
+        return rp, ci[:nnzb.value], bl[:nnzb.value]
 
 
 def _arr(ctype, vals):

@@ -106,6 +106,21 @@ struct sp2_ctx_s {
   std::vector<float> square_ms;
   bool timed = false;
 
+  // block-sparse mode
+  bool bsr = false;
+  struct {
+    int64_t n = 0;
+    int nb = 0, nnzb_in = 0, cap = 0, grid = 0;
+    const double* F = nullptr;
+    sp2::BsrMat m[2] = {};
+    sp2::BsrIndex idx = {};
+    uint32_t* bitmap = nullptr;
+    int32_t* qcnt = nullptr;
+    sp2::BsrCounters* ctr = nullptr;
+    size_t bytes = 0;              // bytes of the allocation below
+    void* mem = nullptr;           // one allocation holding all of the above
+  } b;
+
   // outcome
   bool inited = false, ran = false;
   double run_ms = 0.0;
@@ -137,12 +152,14 @@ sp2_status fail(sp2_ctx c, sp2_status s, const char* what, hipError_t e) {
   } while (0)
 
 // Library choice of square-kernel configuration (0-based id) for one
-// instance of dimension n.
+// instance of dimension n, from timings of every configuration on MI355X
+// at n = 4096 and 8192 (128 x 128 tiles with 2 x 4 waves for FP64/FP32,
+// 256 x 256 with 2 x 4 waves for BF16x3; smaller tiles below 1024).
 int default_config(int precision, int64_t n) {
   switch (precision) {
     case SP2_FP64: return n >= 1024 ? 0 : 2;
-    case SP2_FP32: return 3;
-    default: return n >= 2048 ? 7 : 6;
+    case SP2_FP32: return n >= 1024 ? 4 : 3;
+    default: return n >= 2048 ? 8 : 6;
   }
 }
 
@@ -418,8 +435,14 @@ sp2_status run_batch(sp2_ctx c) {
 
   SP2_HIP(c, hipEventRecord(c->ev_start, s));
   SP2_HIP(c, sp2::launch_state_reset(c->d_st, count, c->d_ndone, s));
-  SP2_HIP(c, sp2::launch_f0(c->d_inst, c->d_f0, c->nf0, c->fp64_store,
-                            c->d_part_f0, s));
+  if (c->bsr) {
+    SP2_HIP(c, sp2::launch_bsr_reset(c->b.ctr, s));
+    SP2_HIP(c, sp2::launch_bsr_f0(c->b.F, c->b.m[0], c->b.nnzb_in, c->d_inst,
+                                  static_cast<int>(c->b.n), c->d_part_f0, s));
+  } else {
+    SP2_HIP(c, sp2::launch_f0(c->d_inst, c->d_f0, c->nf0, c->fp64_store,
+                              c->d_part_f0, s));
+  }
   SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
                                   c->d_ndone, c->mirror, 0, s));
   SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
@@ -430,12 +453,25 @@ sp2_status run_batch(sp2_ctx c) {
   a.ws = c->d_ws;
   a.part = c->d_part;
   int last = 0;
-  for (int i = 1; i <= c->opt.max_iter && !c->groups.empty(); ++i) {
+  const bool any_work = c->bsr || !c->groups.empty();
+  for (int i = 1; i <= c->opt.max_iter && any_work; ++i) {
     if (i > kLookahead)
       SP2_HIP(c, hipEventSynchronize(c->ev_ring[(i - kLookahead) % kRing]));
     if (__atomic_load_n(&c->mirror->all_done, __ATOMIC_ACQUIRE)) break;
     a.iter = i;
     if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i], s));
+    if (c->bsr) {
+      const sp2::BsrMat& cur = c->b.m[(i - 1) & 1];
+      const sp2::BsrMat& nxt = c->b.m[i & 1];
+      SP2_HIP(c, sp2::launch_bsr_index(cur, c->b.nb, c->b.idx, c->d_st, s));
+      SP2_HIP(c, sp2::launch_bsr_symbolic(c->b.idx, c->b.nb, c->b.bitmap,
+                                          c->b.qcnt, nxt, c->b.cap, c->b.ctr,
+                                          c->d_st, s));
+      SP2_HIP(c, sp2::launch_bsr_numeric(cur, c->b.idx, nxt, c->b.ctr,
+                                         c->d_inst, i,
+                                         static_cast<int>(c->b.n), c->d_part,
+                                         c->b.grid, s));
+    }
     for (const Group& g : c->groups) {
       a.items = g.items;
       a.tails = g.tails;
@@ -466,6 +502,17 @@ sp2_status run_batch(sp2_ctx c) {
   }
   c->steps = steps;
   c->run_ms = ms;
+  if (c->bsr) {
+    sp2::BsrCounters ctr;
+    SP2_HIP(c, hipMemcpy(&ctr, c->b.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+    if (ctr.overflow & 1)
+      return fail(c, SP2_OUT_OF_MEMORY,
+                  "block-sparse iterate exceeded the block capacity", hipSuccess);
+    if (ctr.overflow & 2)
+      return fail(c, SP2_INVALID_ARG,
+                  "block pattern lost its symmetry: F is not symmetric",
+                  hipSuccess);
+  }
   if (timing) {
     for (int i = 1; i <= std::min(steps, last); ++i) {
       float t = 0.f;
@@ -478,8 +525,37 @@ sp2_status run_batch(sp2_ctx c) {
   return SP2_OK;
 }
 
+// Index of the nonzero blocks of the returned block-sparse iterate.
+sp2_status bsr_result_index(sp2_ctx c, int64_t* nnzb) {
+  const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
+  SP2_HIP(c, sp2::launch_bsr_index(m, c->b.nb, c->b.idx, nullptr, c->stream));
+  int32_t cnt = 0;
+  SP2_HIP(c, hipMemcpyAsync(&cnt, c->b.idx.ptr + c->b.nb, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  SP2_HIP(c, hipStreamSynchronize(c->stream));
+  *nnzb = cnt;
+  return SP2_OK;
+}
+
 sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
                         int32_t as_fp64) {
+  if (c->bsr) {
+    if (!D_dev || ldd < c->b.n)
+      return fail(c, SP2_INVALID_ARG, "D_dev NULL or ldd < n", hipSuccess);
+    SP2_HIP(c, hipSetDevice(c->device));
+    int64_t nnzb = 0;
+    sp2_status st = bsr_result_index(c, &nnzb);
+    if (st != SP2_OK) return st;
+    const size_t es = as_fp64 ? 8 : 4;
+    SP2_HIP(c, hipMemset2DAsync(D_dev, ldd * es, 0, c->b.n * es, c->b.n,
+                                c->stream));
+    const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
+    SP2_HIP(c, sp2::launch_bsr_to_dense(m.val, c->b.idx, c->b.nb,
+                                        static_cast<int>(c->b.n), D_dev, ldd,
+                                        as_fp64 != 0, c->stream));
+    SP2_HIP(c, hipStreamSynchronize(c->stream));
+    return SP2_OK;
+  }
   const HostInst& h = c->hi[idx];
   if (!D_dev || ldd < h.n)
     return fail(c, SP2_INVALID_ARG, "D_dev NULL or ldd < n", hipSuccess);
@@ -605,6 +681,7 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_f0);
   rel(c->d_ws);
   rel(c->d_ndone);
+  rel(c->b.mem);
   release_groups(c);
   if (c->mirror) (void)hipHostFree(c->mirror);
   if (c->ev_start) (void)hipEventDestroy(c->ev_start);
@@ -653,12 +730,223 @@ sp2_status sp2_batch_init(sp2_ctx c, int32_t count, const double* const* F_dev,
     hi[b].n_occ = n_occ[b];
   }
   SP2_HIP(c, hipSetDevice(c->device));
+  c->bsr = false;
   c->opt = opt;
   c->fp64_store = (opt.precision == SP2_FP64);
   c->hi = std::move(hi);
   st = setup(c);
   if (st != SP2_OK) return st;
   c->inited = true;
+  return SP2_OK;
+}
+
+sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
+                        const int32_t* row_ptr_dev, const int32_t* col_idx_dev,
+                        const double* blocks_dev, double lambda_min,
+                        double lambda_max, int64_t n_occ,
+                        const sp2_options* opt_in) {
+  if (!c) return SP2_INVALID_ARG;
+  c->err.clear();
+  c->inited = false;
+  c->ran = false;
+  sp2_options opt;
+  if (opt_in) {
+    opt = *opt_in;
+  } else {
+    sp2_default_options(&opt);
+    opt.precision = SP2_FP32;
+  }
+  sp2_status st = validate_options(c, opt);
+  if (st != SP2_OK) return st;
+  if (opt.precision != SP2_FP32)
+    return fail(c, SP2_INVALID_ARG, "block-sparse runs use SP2_FP32",
+                hipSuccess);
+  if (block != sp2::kBsrBlock)
+    return fail(c, SP2_INVALID_ARG, "block must be 32", hipSuccess);
+  if (n <= 0 || n > static_cast<int64_t>(sp2::kMaxBlockCols) * sp2::kBsrBlock)
+    return fail(c, SP2_INVALID_ARG, "n must be in [1, 65536]", hipSuccess);
+  if (!row_ptr_dev || !col_idx_dev || !blocks_dev || nnzb <= 0)
+    return fail(c, SP2_INVALID_ARG, "NULL array or nnzb <= 0", hipSuccess);
+  if (n_occ < 0 || n_occ > n)
+    return fail(c, SP2_INVALID_ARG, "n_occ outside [0, n]", hipSuccess);
+  if (!isfinite(lambda_min) || !isfinite(lambda_max) ||
+      !(lambda_max > lambda_min) || !isfinite(lambda_max - lambda_min))
+    return fail(c, SP2_INVALID_ARG,
+                "spectral bounds must be finite with lambda_max > lambda_min",
+                hipSuccess);
+  const int nb = static_cast<int>((n + sp2::kBsrBlock - 1) / sp2::kBsrBlock);
+  if (nnzb > static_cast<int64_t>(nb) * nb)
+    return fail(c, SP2_INVALID_ARG, "nnzb exceeds nb * nb", hipSuccess);
+  SP2_HIP(c, hipSetDevice(c->device));
+  // Validate the pattern on the host: sorted unique columns, every diagonal
+  // block present, and a symmetric pattern.
+  std::vector<int32_t> rp(nb + 1), ci(nnzb);
+  SP2_HIP(c, hipMemcpy(rp.data(), row_ptr_dev, (nb + 1) * sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+  SP2_HIP(c, hipMemcpy(ci.data(), col_idx_dev, nnzb * sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+  if (rp[0] != 0 || rp[nb] != nnzb)
+    return fail(c, SP2_INVALID_ARG, "row_ptr must start at 0 and end at nnzb",
+                hipSuccess);
+  std::vector<int32_t> brow(nnzb);
+  for (int r = 0; r < nb; ++r) {
+    if (rp[r + 1] < rp[r])
+      return fail(c, SP2_INVALID_ARG, "row_ptr not monotone", hipSuccess);
+    bool diag = false;
+    for (int q = rp[r]; q < rp[r + 1]; ++q) {
+      if (ci[q] < 0 || ci[q] >= nb || (q > rp[r] && ci[q] <= ci[q - 1]))
+        return fail(c, SP2_INVALID_ARG,
+                    "column indices out of range or not sorted and unique",
+                    hipSuccess);
+      diag = diag || ci[q] == r;
+      brow[q] = r;
+    }
+    if (!diag)
+      return fail(c, SP2_INVALID_ARG, "every diagonal block must be stored",
+                  hipSuccess);
+  }
+  for (int r = 0; r < nb; ++r)
+    for (int q = rp[r]; q < rp[r + 1]; ++q) {
+      const int cc = ci[q];
+      if (!std::binary_search(ci.begin() + rp[cc], ci.begin() + rp[cc + 1], r))
+        return fail(c, SP2_INVALID_ARG, "block pattern is not symmetric",
+                    hipSuccess);
+    }
+  // Capacity for the fill of the iterates.
+  const int64_t cap64 = std::min<int64_t>(static_cast<int64_t>(nb) * nb,
+                                          16 * nnzb + 64 * nb);
+  const int cap = static_cast<int>(cap64);
+  const int nbw = (nb + 31) / 32;
+  const int grid = 4 * c->num_cus;
+  // One allocation, carved into aligned pieces.
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  size_t o_m[2][5];
+  for (int k = 0; k < 2; ++k) {
+    o_m[k][0] = take((nb + 1) * sizeof(int32_t));
+    o_m[k][1] = take(cap * sizeof(int32_t));
+    o_m[k][2] = take(cap * sizeof(int32_t));
+    o_m[k][3] = take(static_cast<size_t>(cap) * 1024 * sizeof(float));
+    o_m[k][4] = take(cap * sizeof(int32_t));
+  }
+  const size_t o_ip = take((nb + 1) * sizeof(int32_t));
+  const size_t o_ic = take(cap * sizeof(int32_t));
+  const size_t o_is = take(cap * sizeof(int32_t));
+  const size_t o_bm = take(static_cast<size_t>(nb) * nbw * sizeof(uint32_t));
+  const size_t o_qc = take(nb * sizeof(int32_t));
+  const size_t o_ct = take(sizeof(sp2::BsrCounters));
+  if (off > c->b.bytes) {
+    SP2_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->b.mem) (void)hipFree(c->b.mem);
+    c->b.mem = nullptr;
+    c->b.bytes = 0;
+    SP2_HIP(c, hipMalloc(&c->b.mem, off));
+    c->b.bytes = off;
+  }
+  char* base = static_cast<char*>(c->b.mem);
+  for (int k = 0; k < 2; ++k) {
+    c->b.m[k].row_ptr = reinterpret_cast<int32_t*>(base + o_m[k][0]);
+    c->b.m[k].col = reinterpret_cast<int32_t*>(base + o_m[k][1]);
+    c->b.m[k].brow = reinterpret_cast<int32_t*>(base + o_m[k][2]);
+    c->b.m[k].val = reinterpret_cast<float*>(base + o_m[k][3]);
+    c->b.m[k].flag = reinterpret_cast<int32_t*>(base + o_m[k][4]);
+  }
+  c->b.idx.ptr = reinterpret_cast<int32_t*>(base + o_ip);
+  c->b.idx.col = reinterpret_cast<int32_t*>(base + o_ic);
+  c->b.idx.pos = reinterpret_cast<int32_t*>(base + o_is);
+  c->b.bitmap = reinterpret_cast<uint32_t*>(base + o_bm);
+  c->b.qcnt = reinterpret_cast<int32_t*>(base + o_qc);
+  c->b.ctr = reinterpret_cast<sp2::BsrCounters*>(base + o_ct);
+  c->b.n = n;
+  c->b.nb = nb;
+  c->b.nnzb_in = static_cast<int>(nnzb);
+  c->b.cap = cap;
+  c->b.grid = grid;
+  c->b.F = blocks_dev;
+  hipStream_t s = c->stream;
+  // the input pattern becomes the pattern of X_0
+  SP2_HIP(c, hipMemcpyAsync(c->b.m[0].row_ptr, rp.data(),
+                            (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipMemcpyAsync(c->b.m[0].col, ci.data(), nnzb * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipMemcpyAsync(c->b.m[0].brow, brow.data(),
+                            nnzb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // instance table of one entry: partial sums of the numeric kernel (one
+  // triple per workgroup) and of the affine start (one per block)
+  Instance in{};
+  SP2_HIP(c, grow(c->d_st, c->d_st_cap, sizeof(DevState), s));
+  in.n = static_cast<int>(n);
+  in.tile0 = 0;
+  in.ntiles = grid;
+  in.f0blk0 = 0;
+  in.nf0blk = static_cast<int>(nnzb);
+  in.st = c->d_st;
+  in.lmax = lambda_max;
+  in.width = lambda_max - lambda_min;
+  in.tau = opt.trunc_tau;
+  in.prm.n_occ = static_cast<double>(n_occ);
+  in.prm.n = static_cast<double>(n);
+  in.prm.branch = opt.branch;
+  in.prm.max_iter = opt.max_iter;
+  SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, sizeof(Instance), s));
+  SP2_HIP(c, grow(c->d_part, c->d_part_cap, grid * 3 * sizeof(double), s));
+  SP2_HIP(c, grow(c->d_part_f0, c->d_part_f0_cap, nnzb * 3 * sizeof(double), s));
+  SP2_HIP(c, hipMemcpyAsync(c->d_inst, &in, sizeof(Instance),
+                            hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipStreamSynchronize(s));
+  release_groups(c);
+  HostInst h;
+  h.F = nullptr;
+  h.n = n;
+  h.n_occ = n_occ;
+  h.lmin = lambda_min;
+  h.lmax = lambda_max;
+  h.trivial = (n_occ == 0 || n_occ == n);
+  c->hi.assign(1, h);
+  c->opt = opt;
+  c->fp64_store = false;
+  c->bsr = true;
+  c->inited = true;
+  return SP2_OK;
+}
+
+sp2_status sp2_get_bsr_nnzb(sp2_ctx c, int64_t* nnzb) {
+  if (!c || !nnzb) return SP2_INVALID_ARG;
+  if (!c->ran || !c->bsr)
+    return fail(c, SP2_BAD_STATE, "no completed block-sparse run", hipSuccess);
+  SP2_HIP(c, hipSetDevice(c->device));
+  return bsr_result_index(c, nnzb);
+}
+
+sp2_status sp2_get_bsr(sp2_ctx c, int32_t* row_ptr_dev, int32_t* col_idx_dev,
+                       void* blocks_dev, int32_t as_fp64) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran || !c->bsr)
+    return fail(c, SP2_BAD_STATE, "no completed block-sparse run", hipSuccess);
+  if (!row_ptr_dev || !col_idx_dev || !blocks_dev)
+    return fail(c, SP2_INVALID_ARG, "NULL output array", hipSuccess);
+  SP2_HIP(c, hipSetDevice(c->device));
+  int64_t nnzb = 0;
+  sp2_status st = bsr_result_index(c, &nnzb);
+  if (st != SP2_OK) return st;
+  hipStream_t s = c->stream;
+  SP2_HIP(c, hipMemcpyAsync(row_ptr_dev, c->b.idx.ptr,
+                            (c->b.nb + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+  if (nnzb > 0) {
+    SP2_HIP(c, hipMemcpyAsync(col_idx_dev, c->b.idx.col,
+                              nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              s));
+    const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
+    SP2_HIP(c, sp2::launch_bsr_gather(m.val, c->b.idx.pos,
+                                      static_cast<int>(nnzb), blocks_dev,
+                                      as_fp64 != 0, s));
+  }
+  SP2_HIP(c, hipStreamSynchronize(s));
   return SP2_OK;
 }
 

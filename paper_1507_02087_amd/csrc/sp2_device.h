@@ -129,6 +129,52 @@ hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
                            void* D, int64_t ldd, bool out_fp64,
                            hipStream_t s);
 
+// ---- Block-sparse (BSR, 32 x 32 FP32 blocks) path.
+constexpr int kBsrBlock = 32;
+constexpr int kMaxBlockCols = 2048;   // block rows/columns: n <= 65536
+
+// One block-sparse iterate: both triangles stored, columns sorted per row.
+struct BsrMat {
+  int32_t* row_ptr;   // nb + 1
+  int32_t* col;       // capacity
+  int32_t* brow;      // capacity: block row of each stored block
+  float* val;         // capacity * 32 * 32, row-major blocks
+  int32_t* flag;      // capacity: 1 if the block holds a nonzero
+};
+
+// Nonzero blocks of an iterate, per row: columns and storage positions.
+struct BsrIndex {
+  int32_t* ptr;       // nb + 1
+  int32_t* col;
+  int32_t* pos;
+};
+
+struct BsrCounters {
+  int32_t nnzb;       // stored blocks of the pattern being built
+  int32_t overflow;   // 1: capacity exceeded; 2: pattern not symmetric
+  int32_t pad[2];
+};
+
+hipError_t launch_bsr_reset(BsrCounters* ctr, hipStream_t s);
+hipError_t launch_bsr_index(const BsrMat& M, int nb, const BsrIndex& idx,
+                            const DevState* st, hipStream_t s);
+hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
+                               int32_t* qcnt, const BsrMat& Q, int32_t cap,
+                               BsrCounters* ctr, const DevState* st,
+                               hipStream_t s);
+hipError_t launch_bsr_numeric(const BsrMat& A, const BsrIndex& idx,
+                              const BsrMat& B, BsrCounters* ctr,
+                              const Instance* inst, int iter, int n,
+                              double* part, int grid, hipStream_t s);
+hipError_t launch_bsr_f0(const double* F, const BsrMat& X, int nnzb,
+                         const Instance* inst, int n, double* part,
+                         hipStream_t s);
+hipError_t launch_bsr_gather(const float* val, const int32_t* pos, int cnt,
+                             void* out, bool fp64, hipStream_t s);
+hipError_t launch_bsr_to_dense(const float* val, const BsrIndex& idx, int nb,
+                               int n, void* D, int64_t ldd, bool fp64,
+                               hipStream_t s);
+
 int kernel_config_count();
 const KernelConfig* kernel_config(int id);   // id in [0, count)
 // Launches the main square kernel of configuration `id` with `grid`
