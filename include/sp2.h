@@ -211,6 +211,15 @@ sp2_status sp2_get_bsr_nnzb(sp2_ctx ctx, int64_t* nnzb);
 sp2_status sp2_get_bsr(sp2_ctx ctx, int32_t* row_ptr_dev, int32_t* col_idx_dev,
                        void* blocks_dev, int32_t as_fp64);
 
+/* Work of the last block-sparse run, per step i + 1 (i = 0 .. len-1):
+ * stored[i] = blocks of the pattern of X~_{i+1} (the symbolic product),
+ * nonzero[i] = nonzero blocks of X~_i that entered the product, products[i]
+ * = 32 x 32 block products X_IK X_JK^T computed for the upper blocks.
+ * *len receives the number of squares. Any array may be NULL. */
+sp2_status sp2_get_bsr_stats(sp2_ctx ctx, int32_t cap, int32_t* len,
+                             int64_t* stored, int64_t* nonzero,
+                             int64_t* products);
+
 /* ---- Batched purification: many independent matrices, one launch
  * sequence per step, each instance with its own polynomial choices and its
  * own stop (Alg. 2 applied to every instance). A dense run (sp2_init_dense)

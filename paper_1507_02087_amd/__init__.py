@@ -46,6 +46,8 @@ SIGNATURES = {
     "sp2_get_bsr_nnzb": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64)]),
     "sp2_get_bsr": (_c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                _c.c_int32]),
+    "sp2_get_bsr_stats": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
+                                     _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     "sp2_batch_init": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]),
@@ -299,6 +301,18 @@ class BsrContext(Context):
                                           ctypes.c_void_p(bl.data_ptr()),
                                           1 if as_fp64 else 0), "sp2_get_bsr")
         return rp, ci[:nnzb.value], bl[:nnzb.value]
+
+    def get_bsr_stats(self):
+        """Per step: stored blocks, nonzero input blocks, block products."""
+        import numpy as np
+        cap = MAX_ITER_LIMIT + 1
+        ln = ctypes.c_int32()
+        a, b, c = (np.zeros(cap, dtype=np.int64) for _ in range(3))
+        ptr = lambda x: ctypes.c_void_p(x.ctypes.data)  # noqa: E731
+        self._check(self._lib.sp2_get_bsr_stats(self._h, cap, ctypes.byref(ln), ptr(a),
+                                                ptr(b), ptr(c)), "sp2_get_bsr_stats")
+        m = ln.value
+        return dict(stored=a[:m].tolist(), nonzero=b[:m].tolist(), products=c[:m].tolist())
 
 
 def _arr(ctype, vals):

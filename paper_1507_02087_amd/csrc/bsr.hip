@@ -58,7 +58,8 @@ __device__ void block_exclusive_scan(const int32_t* cnt, int n, int32_t* out,
 
 // (1) Index of the nonzero blocks of M, per row, in column order.
 __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
-    BsrMat M, int nb, BsrIndex idx, const DevState* st) {
+    BsrMat M, int nb, BsrIndex idx, const DevState* st, BsrCounters* ctr,
+    int iter) {
   __shared__ int32_t cnt[2 * kScanThreads];
   __shared__ int32_t sh[kScanThreads];
   if (st && st->done) return;
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
   __syncthreads();
   block_exclusive_scan(cnt, nb, idx.ptr, sh);
   __syncthreads();
+  if (iter > 0 && threadIdx.x == 0) ctr->nonzero[iter] = idx.ptr[nb];
   for (int r = threadIdx.x; r < nb; r += kScanThreads) {
     int o = idx.ptr[r];
     for (int q = M.row_ptr[r]; q < M.row_ptr[r + 1]; ++q)
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(256) void bsr_symbolic_count_kernel(
 // (2b) Row pointers of Q; flags an overflow when Q exceeds the capacity.
 __global__ __launch_bounds__(kScanThreads) void bsr_symbolic_scan_kernel(
     const int32_t* qcnt, int nb, int32_t* row_ptr, int32_t cap,
-    BsrCounters* ctr, const DevState* st) {
+    BsrCounters* ctr, const DevState* st, int iter) {
   __shared__ int32_t cnt[2 * kScanThreads];
   __shared__ int32_t sh[kScanThreads];
   if (st->done) return;
@@ -126,6 +128,7 @@ __global__ __launch_bounds__(kScanThreads) void bsr_symbolic_scan_kernel(
   if (threadIdx.x == 0) {
     const int total = row_ptr[nb];
     ctr->nnzb = total;
+    ctr->stored[iter] = total;
     if (total > cap) ctr->overflow = 1;
   }
 }
@@ -199,6 +202,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
   const int total = ctr->nnzb;
   const int G = gridDim.x * 4;
   double sv = 0.0, st1 = 0.0, st2 = 0.0;
+  unsigned long long nprod = 0;
   for (int q = blockIdx.x * 4 + wave; q < total; q += G) {
     const int I = B.brow[q], J = B.col[q];
     if (J < I) continue;
@@ -218,6 +222,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
         }
       }
       unsigned long long mask = __ballot(posI >= 0);
+      nprod += __popcll(mask);
       while (mask) {
         const int src = __ffsll(static_cast<long long>(mask)) - 1;
         mask &= mask - 1;
@@ -284,6 +289,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     sh[wave][2] = st2;
   }
   __syncthreads();
+  if (lane == 0 && nprod) atomicAdd(&ctr->products[iter], nprod);
   if (threadIdx.x == 0) {
     part[3 * blockIdx.x + 0] = sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0];
     part[3 * blockIdx.x + 1] = sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1];
@@ -346,10 +352,9 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(
 }
 
 __global__ void bsr_reset_kernel(BsrCounters* ctr) {
-  if (threadIdx.x == 0) {
-    ctr->nnzb = 0;
-    ctr->overflow = 0;
-  }
+  int32_t* w = reinterpret_cast<int32_t*>(ctr);
+  const int words = static_cast<int>(sizeof(BsrCounters) / sizeof(int32_t));
+  for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
 }
 
 // Gathers the blocks listed by idx.pos into a compact array (FP64 or FP32).
@@ -389,15 +394,16 @@ hipError_t launch_bsr_reset(BsrCounters* ctr, hipStream_t s) {
 }
 
 hipError_t launch_bsr_index(const BsrMat& M, int nb, const BsrIndex& idx,
-                            const DevState* st, hipStream_t s) {
+                            const DevState* st, BsrCounters* ctr, int iter,
+                            hipStream_t s) {
   hipLaunchKernelGGL(bsr_index_kernel, dim3(1), dim3(kScanThreads), 0, s, M,
-                     nb, idx, st);
+                     nb, idx, st, ctr, iter);
   return hipGetLastError();
 }
 
 hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
                                int32_t* qcnt, const BsrMat& Q, int32_t cap,
-                               BsrCounters* ctr, const DevState* st,
+                               BsrCounters* ctr, const DevState* st, int iter,
                                hipStream_t s) {
   const int nbw = (nb + 31) / 32;
   hipLaunchKernelGGL(bsr_symbolic_count_kernel, dim3(nb), dim3(256), 0, s, idx,
@@ -405,7 +411,7 @@ hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bsr_symbolic_scan_kernel, dim3(1), dim3(kScanThreads), 0,
-                     s, qcnt, nb, Q.row_ptr, cap, ctr, st);
+                     s, qcnt, nb, Q.row_ptr, cap, ctr, st, iter);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bsr_symbolic_fill_kernel, dim3(nb), dim3(64), 0, s,

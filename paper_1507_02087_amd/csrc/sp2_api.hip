@@ -117,6 +117,7 @@ struct sp2_ctx_s {
     uint32_t* bitmap = nullptr;
     int32_t* qcnt = nullptr;
     sp2::BsrCounters* ctr = nullptr;
+    sp2::BsrCounters host_ctr = {};   // counters of the last run
     size_t bytes = 0;              // bytes of the allocation below
     void* mem = nullptr;           // one allocation holding all of the above
   } b;
@@ -463,10 +464,11 @@ sp2_status run_batch(sp2_ctx c) {
     if (c->bsr) {
       const sp2::BsrMat& cur = c->b.m[(i - 1) & 1];
       const sp2::BsrMat& nxt = c->b.m[i & 1];
-      SP2_HIP(c, sp2::launch_bsr_index(cur, c->b.nb, c->b.idx, c->d_st, s));
+      SP2_HIP(c, sp2::launch_bsr_index(cur, c->b.nb, c->b.idx, c->d_st,
+                                       c->b.ctr, i, s));
       SP2_HIP(c, sp2::launch_bsr_symbolic(c->b.idx, c->b.nb, c->b.bitmap,
                                           c->b.qcnt, nxt, c->b.cap, c->b.ctr,
-                                          c->d_st, s));
+                                          c->d_st, i, s));
       SP2_HIP(c, sp2::launch_bsr_numeric(cur, c->b.idx, nxt, c->b.ctr,
                                          c->d_inst, i,
                                          static_cast<int>(c->b.n), c->d_part,
@@ -503,7 +505,7 @@ sp2_status run_batch(sp2_ctx c) {
   c->steps = steps;
   c->run_ms = ms;
   if (c->bsr) {
-    sp2::BsrCounters ctr;
+    sp2::BsrCounters& ctr = c->b.host_ctr;
     SP2_HIP(c, hipMemcpy(&ctr, c->b.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
     if (ctr.overflow & 1)
       return fail(c, SP2_OUT_OF_MEMORY,
@@ -528,7 +530,8 @@ sp2_status run_batch(sp2_ctx c) {
 // Index of the nonzero blocks of the returned block-sparse iterate.
 sp2_status bsr_result_index(sp2_ctx c, int64_t* nnzb) {
   const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
-  SP2_HIP(c, sp2::launch_bsr_index(m, c->b.nb, c->b.idx, nullptr, c->stream));
+  SP2_HIP(c, sp2::launch_bsr_index(m, c->b.nb, c->b.idx, nullptr, c->b.ctr, 0,
+                                   c->stream));
   int32_t cnt = 0;
   SP2_HIP(c, hipMemcpyAsync(&cnt, c->b.idx.ptr + c->b.nb, sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
@@ -947,6 +950,23 @@ sp2_status sp2_get_bsr(sp2_ctx c, int32_t* row_ptr_dev, int32_t* col_idx_dev,
                                       as_fp64 != 0, s));
   }
   SP2_HIP(c, hipStreamSynchronize(s));
+  return SP2_OK;
+}
+
+sp2_status sp2_get_bsr_stats(sp2_ctx c, int32_t cap, int32_t* len,
+                             int64_t* stored, int64_t* nonzero,
+                             int64_t* products) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran || !c->bsr)
+    return fail(c, SP2_BAD_STATE, "no completed block-sparse run", hipSuccess);
+  const sp2::BsrCounters& h = c->b.host_ctr;
+  const int m = c->hi[0].trivial ? 0 : c->host_state[0].squares;
+  if (len) *len = m;
+  for (int i = 0; i < cap && i < m; ++i) {
+    if (stored) stored[i] = h.stored[i + 1];
+    if (nonzero) nonzero[i] = h.nonzero[i + 1];
+    if (products) products[i] = static_cast<int64_t>(h.products[i + 1]);
+  }
   return SP2_OK;
 }
 

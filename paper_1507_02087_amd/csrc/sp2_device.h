@@ -153,14 +153,21 @@ struct BsrCounters {
   int32_t nnzb;       // stored blocks of the pattern being built
   int32_t overflow;   // 1: capacity exceeded; 2: pattern not symmetric
   int32_t pad[2];
+  // per step i: blocks of the pattern of X~_i, nonzero blocks of X~_{i-1},
+  // and block products X_IK X_JK^T computed
+  int32_t stored[kMaxIter + 2];
+  int32_t nonzero[kMaxIter + 2];
+  unsigned long long products[kMaxIter + 2];
 };
 
 hipError_t launch_bsr_reset(BsrCounters* ctr, hipStream_t s);
+// iter > 0 records the count of nonzero blocks in ctr->nonzero[iter].
 hipError_t launch_bsr_index(const BsrMat& M, int nb, const BsrIndex& idx,
-                            const DevState* st, hipStream_t s);
+                            const DevState* st, BsrCounters* ctr, int iter,
+                            hipStream_t s);
 hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
                                int32_t* qcnt, const BsrMat& Q, int32_t cap,
-                               BsrCounters* ctr, const DevState* st,
+                               BsrCounters* ctr, const DevState* st, int iter,
                                hipStream_t s);
 hipError_t launch_bsr_numeric(const BsrMat& A, const BsrIndex& idx,
                               const BsrMat& B, BsrCounters* ctr,
