@@ -256,6 +256,9 @@ def main() -> int:
     ap.add_argument("--cpu-squares", type=int, default=5)
     ap.add_argument("--config", type=int, default=0,
                     help="square-kernel configuration id (0 = library choice)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB twice with torch (a plain copy "
+                         "kernel of known size, to scale HBM byte counters)")
     ap.add_argument("--workload", default="dense", choices=["dense", "batch", "bsr"],
                     help="dense: N=8192 mixed vs FP64 (the headline); batch: 512 "
                          "instances of uneven N in FP32; bsr: block-sparse N=32768")
@@ -371,6 +374,15 @@ def main() -> int:
             "per_launch_flops": exec_flops,
         },
     }
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
 
     if not args.no_fp64 and prec != "fp64":
         log("[bench] FP64 comparison run")

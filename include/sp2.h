@@ -263,6 +263,18 @@ sp2_status sp2_batch_get_history(sp2_ctx ctx, int32_t idx, int32_t cap,
 sp2_status sp2_batch_get_run_time(sp2_ctx ctx, double* run_ms,
                                   int32_t* steps);
 
+/* Installs a table that chooses the square-kernel configuration per
+ * instance when opt->kernel_config is 0: for an instance of dimension n and
+ * precision p, the first entry e (in the given order) with precision[e] == p
+ * and n <= n_max[e] gives the 1-based configuration config_id[e]; instances
+ * no entry covers use the library's built-in choice. count = 0 removes the
+ * table. The table is copied; it applies to later sp2_init_dense and
+ * sp2_batch_init calls on this context. Errors: SP2_INVALID_ARG (unknown
+ * configuration id or one whose precision differs from the entry's). */
+sp2_status sp2_set_kernel_table(sp2_ctx ctx, int32_t count,
+                                const int32_t* precision, const int64_t* n_max,
+                                const int32_t* config_id);
+
 /* Number of compiled square-kernel configurations (ids 1..count). */
 int32_t sp2_kernel_config_count(void);
 

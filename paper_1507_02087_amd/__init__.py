@@ -14,6 +14,8 @@ from dataclasses import dataclass, field
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsp2.so")
+# Square-kernel choices per size, written by autotune.py on an MI355X.
+TABLE_PATH = os.path.join(HERE, "kernel_table_mi355x.json")
 
 # sp2_status
 OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, DIVERGED, BAD_STATE = range(7)
@@ -61,6 +63,8 @@ SIGNATURES = {
                                          _c.c_void_p]),
     "sp2_batch_get_run_time": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double),
                                           _c.POINTER(_c.c_int32)]),
+    "sp2_set_kernel_table": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                        _c.c_void_p]),
     "sp2_kernel_config_count": (_c.c_int32, []),
     "sp2_kernel_config_info": (_c.c_int, [_c.c_int32] + [_c.POINTER(_c.c_int32)] * 5),
     "sp2_status_string": (_c.c_char_p, [_c.c_int]),
@@ -155,6 +159,35 @@ class Context:
         self._h = h
         self._n = 0
         self._prec = "fp64"
+        if os.path.exists(TABLE_PATH):
+            self.load_kernel_table(TABLE_PATH)
+
+    def set_kernel_table(self, entries):
+        """entries: list of (precision name, n_max, 1-based config id); the
+        first entry matching an instance's precision with n <= n_max picks
+        its square-kernel configuration."""
+        cnt = len(entries)
+        prec = (ctypes.c_int32 * max(1, cnt))(*[PRECISIONS[e[0]] for e in entries])
+        nmax = (ctypes.c_int64 * max(1, cnt))(*[int(e[1]) for e in entries])
+        cid = (ctypes.c_int32 * max(1, cnt))(*[int(e[2]) for e in entries])
+        self._check(self._lib.sp2_set_kernel_table(self._h, cnt, prec, nmax, cid),
+                    "sp2_set_kernel_table")
+
+    def load_kernel_table(self, path: str | None = None):
+        """Installs the autotuned table (JSON written by autotune.py)."""
+        import json
+        path = path or TABLE_PATH
+        with open(path) as fh:
+            data = json.load(fh)
+        ids = {(c["precision"], c["tile"], c["waves_m"], c["waves_n"], c["k_slice"]): c["id"]
+               for c in kernel_configs()}
+        entries = []
+        for e in data["entries"]:
+            key = (e["precision"], e["tile"], e["waves_m"], e["waves_n"], e["k_slice"])
+            if key in ids:
+                entries.append((e["precision"], e["n_max"], ids[key]))
+        self.set_kernel_table(entries)
+        return entries
 
     def close(self):
         if getattr(self, "_h", None):

@@ -231,8 +231,8 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
         const float* bb = A.val + static_cast<size_t>(pb) * BE + r * BS + h * 16;
         floatx4 af[4], bf[4];
         for (int u = 0; u < 4; ++u) {
-          af[u] = *reinterpret_cast<const floatx4*>(ab + 4 * u);
-          bf[u] = *reinterpret_cast<const floatx4*>(bb + 4 * u);
+          af[u] = *gro(reinterpret_cast<const floatx4*>(ab + 4 * u));
+          bf[u] = *gro(reinterpret_cast<const floatx4*>(bb + 4 * u));
         }
         for (int s = 0; s < 16; ++s)
           acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s >> 2][s & 3],
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       const int c = r;                                // column in the block
       if (I == J && m > c) continue;
       const float s = acc[j];
-      const float xo = old ? old[m * BS + c] : 0.f;
+      const float xo = old ? *gro(old + m * BS + c) : 0.f;
       const double d = static_cast<double>(xo) - static_cast<double>(s);
       const double w = (I == J && m == c) ? 1.0 : 2.0;
       sv += w * d * d;
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       st2 += w * xd * xd;
       if (I == J && m == c) st1 += xd;
       nz = nz || (xn != 0.f);
-      out[m * BS + c] = xn;
-      if (!(I == J && m == c)) outT[c * BS + m] = xn;
+      *grw(out + m * BS + c) = xn;
+      if (!(I == J && m == c)) *grw(outT + c * BS + m) = xn;
     }
     const int any = __any(nz) ? 1 : 0;
     if (lane == 0) {

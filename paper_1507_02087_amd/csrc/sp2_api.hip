@@ -74,6 +74,14 @@ struct sp2_ctx_s {
   std::string err;
   int num_cus = 256;
 
+  // configuration table: (precision, n_max, 0-based config id)
+  struct TableEntry {
+    int precision;
+    int64_t n_max;
+    int cfg;
+  };
+  std::vector<TableEntry> table;
+
   // problem
   sp2_options opt{};
   bool fp64_store = true;
@@ -154,13 +162,15 @@ sp2_status fail(sp2_ctx c, sp2_status s, const char* what, hipError_t e) {
 
 // Library choice of square-kernel configuration (0-based id) for one
 // instance of dimension n, from timings of every configuration on MI355X
-// at n = 4096 and 8192 (128 x 128 tiles with 2 x 4 waves for FP64/FP32,
-// 256 x 256 with 2 x 4 waves for BF16x3; smaller tiles below 1024).
+// at n = 4096 and 8192 (128 x 128 tiles with 2 x 4 waves for FP64/FP32;
+// for BF16x3 the swizzled 256 x 256 tile with 2 x 4 waves at n = 8192 and
+// the swizzled 128 x 128 tile below). An autotuned table installed with
+// sp2_set_kernel_table takes precedence.
 int default_config(int precision, int64_t n) {
   switch (precision) {
     case SP2_FP64: return n >= 1024 ? 0 : 2;
     case SP2_FP32: return n >= 1024 ? 4 : 3;
-    default: return n >= 2048 ? 8 : 6;
+    default: return n >= 6144 ? 9 : 11;
   }
 }
 
@@ -309,6 +319,12 @@ sp2_status setup(sp2_ctx c) {
   for (HostInst& h : c->hi) {
     h.cfg = c->opt.kernel_config ? c->opt.kernel_config - 1
                                  : default_config(c->opt.precision, h.n);
+    if (!c->opt.kernel_config)
+      for (const auto& e : c->table)
+        if (e.precision == c->opt.precision && h.n <= e.n_max) {
+          h.cfg = e.cfg;
+          break;
+        }
     const int bm = sp2::kernel_config(h.cfg)->bm;
     h.np = ((h.n + bm - 1) / bm) * bm;
     h.xoff = pool_elems;
@@ -621,6 +637,25 @@ const char* sp2_status_string(sp2_status s) {
 const char* sp2_last_error(sp2_ctx ctx) { return ctx ? ctx->err.c_str() : ""; }
 
 int32_t sp2_kernel_config_count(void) { return sp2::kernel_config_count(); }
+
+sp2_status sp2_set_kernel_table(sp2_ctx c, int32_t count,
+                                const int32_t* precision, const int64_t* n_max,
+                                const int32_t* config_id) {
+  if (!c || count < 0) return SP2_INVALID_ARG;
+  if (count > 0 && (!precision || !n_max || !config_id))
+    return fail(c, SP2_INVALID_ARG, "NULL table array", hipSuccess);
+  std::vector<sp2_ctx_s::TableEntry> t;
+  for (int e = 0; e < count; ++e) {
+    const sp2::KernelConfig* kc = sp2::kernel_config(config_id[e] - 1);
+    if (!kc || kc->precision != precision[e])
+      return fail(c, SP2_INVALID_ARG,
+                  "table entry names an unknown configuration or one of "
+                  "another precision", hipSuccess);
+    t.push_back({precision[e], n_max[e], config_id[e] - 1});
+  }
+  c->table = std::move(t);
+  return SP2_OK;
+}
 
 sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
                                   int32_t* tile, int32_t* waves_m,

@@ -12,6 +12,22 @@
 
 namespace sp2 {
 
+// Pointers into global memory as the kernels use them. Addresses that the
+// kernels read from tables in memory are generic to the compiler, which
+// then emits flat loads and stores; flat accesses are tracked together with
+// LDS accesses, so waiting for an LDS read would also wait for every global
+// prefetch in flight. Casting to the global address space gives global
+// loads and stores with their own counter.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gro(
+    const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* grw(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
 // Largest number of squares one run may compute (public SP2_MAX_ITER_LIMIT).
 constexpr int kMaxIter = 200;
 // Rows of X_0 per workgroup of the affine-start kernel.

@@ -101,14 +101,15 @@ __device__ __forceinline__ void epilogue_at(const T* __restrict__ X,
   const int gr = I * BM + lr, gc = J * BM + lc;
   const size_t idx = static_cast<size_t>(gr) * ld + gc;
   if (I != J) {
-    const T xn = epilogue_elem<T>(s, X[idx], p, tau, 2.0, false, sums);
-    Y[idx] = xn;
-    Y[static_cast<size_t>(gc) * ld + gr] = xn;
+    const T xn = epilogue_elem<T>(s, *gro(X + idx), p, tau, 2.0, false, sums);
+    *grw(Y + idx) = xn;
+    *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
   } else if (gr <= gc) {
     const bool on = (gr == gc);
-    const T xn = epilogue_elem<T>(s, X[idx], p, tau, on ? 1.0 : 2.0, on, sums);
-    Y[idx] = xn;
-    if (!on) Y[static_cast<size_t>(gc) * ld + gr] = xn;
+    const T xn = epilogue_elem<T>(s, *gro(X + idx), p, tau, on ? 1.0 : 2.0, on,
+                                  sums);
+    *grw(Y + idx) = xn;
+    if (!on) *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
   }
 }
 
@@ -134,8 +135,8 @@ struct Stage {
     for (int q = 0; q < NCH; ++q) {
       const size_t off =
           static_cast<size_t>(row(tid, q)) * ld + k0 + col(tid, q);
-      a[q] = *reinterpret_cast<const vec*>(Ap + off);
-      b[q] = *reinterpret_cast<const vec*>(Bp + off);
+      a[q] = *gro(reinterpret_cast<const vec*>(Ap + off));
+      b[q] = *gro(reinterpret_cast<const vec*>(Bp + off));
     }
   }
 };
@@ -483,6 +484,173 @@ __device__ __forceinline__ void mainloop_b3(const StepCtx<float>& sc,
   }
 }
 
+// ============================================================== BF16x3, v2
+// Same arithmetic as above with an unpadded LDS layout: every 16-byte chunk
+// (8 bf16 along k) of a row is stored at chunk position c ^ g(row), where
+// g spreads 16 consecutive rows over the 16 distinct 16-byte slots of a
+// 256-byte LDS line, so both the fragment reads (16 rows, same chunk) and
+// the staging writes (whole rows) are free of bank conflicts. The smaller
+// footprint allows K slices of 32 (two MFMA substeps per barrier) with
+// double buffering. The epilogue stages the tile through LDS so that both
+// the tile and its transpose are written in whole rows.
+template <int BM_, int WM_, int WN_, int BK_>
+struct CfgB3S {
+  using T = float;
+  static constexpr int BM = BM_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int TM = BM / WM, TN = BM / WN;
+  static constexpr int MB = TM / 32, NB = TN / 32;
+  static constexpr int KH = BK / 2;     // k values per lane half per slice
+  static constexpr int ARR = BM * BK;   // bf16 per staged array
+  static constexpr int MAIN_BYTES = 2 * 4 * ARR * 2;
+  static constexpr int EPI_BYTES = TM * (BM + 1) * 4;
+  static constexpr int SMEM = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
+  struct Acc {
+    floatx16 c[MB][NB];
+  };
+};
+
+// Element offset of (row, k) in a swizzled [rows][BK] bf16 array.
+template <int BK>
+__device__ __forceinline__ int swz_off(int row, int k) {
+  constexpr int CH = BK / 8;                                  // chunks per row
+  constexpr int SHIFT = BK == 16 ? 3 : (BK == 32 ? 2 : 1);    // log2(128 / BK)
+  const int chunk = (k >> 3) ^ ((row >> SHIFT) & (CH - 1));
+  return row * BK + (chunk << 3) + (k & 7);
+}
+
+template <class C>
+__device__ __forceinline__ void mainloop_b3s(const StepCtx<float>& sc,
+                                             const WorkItem& w,
+                                             typename C::Acc& acc,
+                                             char* smem) {
+  using T = float;
+  __bf16* lds = reinterpret_cast<__bf16*>(smem);
+  // array a (0 AH, 1 AL, 2 BH, 3 BL) of buffer b
+  auto arr = [&](int b, int a) { return lds + (b * 4 + a) * C::ARR; };
+  const int2 tt = sc.tile;
+  const int ld = sc.ld;
+  const T* X = sc.X;
+  const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
+  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  const int r = lane & 31, h = lane >> 5;
+  using St = Stage<T, C::BM, C::BK, C::THREADS>;
+  St st;
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < St::NCH; ++q) {
+      const int rr = St::row(tid, q), cc = St::col(tid, q);
+      const int o = swz_off<C::BK>(rr, cc);
+      bf16x4 hi, lo;
+      split_bf16(st.a[q], hi, lo);
+      *reinterpret_cast<bf16x4*>(arr(b, 0) + o) = hi;
+      *reinterpret_cast<bf16x4*>(arr(b, 1) + o) = lo;
+      split_bf16(st.b[q], hi, lo);
+      *reinterpret_cast<bf16x4*>(arr(b, 2) + o) = hi;
+      *reinterpret_cast<bf16x4*>(arr(b, 3) + o) = lo;
+    }
+  };
+  acc_zero<C>(acc);
+  st.load(Ap, Bp, ld, w.k0 * C::BK, tid);
+  sstore(0);
+  __syncthreads();
+  for (int kt = w.k0; kt < w.k1; ++kt) {
+    const int b = (kt - w.k0) & 1;
+    if (kt + 1 < w.k1) st.load(Ap, Bp, ld, (kt + 1) * C::BK, tid);
+#pragma unroll
+    for (int s8 = 0; s8 < C::KH; s8 += 8) {
+      bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) {
+        const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
+        ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
+        al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
+      }
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n) {
+        const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
+        bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
+        bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
+      }
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n) {
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bh[n], acc.c[m][n], 0, 0, 0);
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bl[n], acc.c[m][n], 0, 0, 0);
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              al[m], bh[n], acc.c[m][n], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < w.k1) sstore(b ^ 1);
+    __syncthreads();
+  }
+}
+
+// Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
+// (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
+// The tile is processed one band of TM rows at a time (the rows of one row
+// of waves): the waves of the band write their accumulators to LDS, then all
+// threads apply the element epilogue in row order (coalesced reads of X and
+// writes of the tile) and write the transposed band in row order of the
+// transpose (coalesced), reading LDS down columns (padding: no conflicts).
+template <class C>
+__device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
+                                                 double* part, int slot,
+                                                 const typename C::Acc& acc,
+                                                 char* smem) {
+  using T = float;
+  constexpr int BM = C::BM, TM = C::TM, LD = BM + 1;
+  T* S = reinterpret_cast<T*>(smem);
+  const int2 tt = sc.tile;
+  const int I = tt.x, J = tt.y;
+  const bool diag = (I == J);
+  const int ld = sc.ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wg = wave / C::WN, wn = (wave % C::WN) * C::TN;
+  Sums sums;
+  for (int g = 0; g < C::WM; ++g) {
+    __syncthreads();
+    if (wg == g) {
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n)
+#pragma unroll
+          for (int j = 0; j < 16; ++j) {
+            const int rr = m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+            const int cc = wn + n * 32 + (lane & 31);
+            S[rr * LD + cc] = acc.c[m][n][j];
+          }
+    }
+    __syncthreads();
+    const int r0 = I * BM + g * TM;
+    for (int e = tid; e < TM * BM; e += C::THREADS) {
+      const int rr = e / BM, cc = e % BM;
+      const int gr = r0 + rr, gc = J * BM + cc;
+      if (diag && gr > gc) continue;
+      const size_t idx = static_cast<size_t>(gr) * ld + gc;
+      const bool on = (gr == gc);
+      const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx), sc.p,
+                                    sc.tau, on ? 1.0 : 2.0, on, sums);
+      *grw(sc.Y + idx) = xn;
+      S[rr * LD + cc] = xn;
+    }
+    __syncthreads();
+    for (int e = tid; e < TM * BM; e += C::THREADS) {
+      const int cc = e / TM, rr = e % TM;
+      const int gr = r0 + rr, gc = J * BM + cc;
+      if (diag && gr >= gc) continue;
+      *grw(sc.Y + static_cast<size_t>(gc) * ld + gr) = S[rr * LD + cc];
+    }
+  }
+  store_partials<C::THREADS>(sums, part, slot);
+}
+
 // ============================================================== drivers
 // Accumulator registers are stored to the workspace as [reg][thread] so
 // that every store and load is coalesced across the workgroup.
@@ -498,7 +666,7 @@ __device__ __forceinline__ void ws_store(const typename C::Acc& acc,
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < PER; ++j, ++k)
-        ws[static_cast<size_t>(k) * C::THREADS + tid] = acc.c[m][n][j];
+        *grw(ws + static_cast<size_t>(k) * C::THREADS + tid) = acc.c[m][n][j];
 }
 
 template <class C>
@@ -513,7 +681,7 @@ __device__ __forceinline__ void ws_accumulate(typename C::Acc& acc,
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < PER; ++j, ++k)
-        acc.c[m][n][j] += ws[static_cast<size_t>(k) * C::THREADS + tid];
+        acc.c[m][n][j] += *gro(ws + static_cast<size_t>(k) * C::THREADS + tid);
 }
 
 template <class C>
@@ -522,13 +690,14 @@ struct Ops;
 template <int A, int B, int Cc, int D>
 struct Ops<CfgF64<A, B, Cc, D>> {
   using C = CfgF64<A, B, Cc, D>;
+  static constexpr int kSmem = 16;   // the main loop declares its own LDS
   using T = typename C::T;
   __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc) {
+                              typename C::Acc& acc, char*) {
     mainloop_f64<C>(sc, w, acc);
   }
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc) {
+                             const typename C::Acc& acc, char*) {
     epilogue_f64<C>(sc, part, slot, acc);
   }
 };
@@ -536,13 +705,14 @@ struct Ops<CfgF64<A, B, Cc, D>> {
 template <int A, int B, int Cc, int D>
 struct Ops<CfgF32<A, B, Cc, D>> {
   using C = CfgF32<A, B, Cc, D>;
+  static constexpr int kSmem = 16;
   using T = typename C::T;
   __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc) {
+                              typename C::Acc& acc, char*) {
     mainloop_f32<C>(sc, w, acc);
   }
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc) {
+                             const typename C::Acc& acc, char*) {
     epilogue_f32<C>(sc, part, slot, acc);
   }
 };
@@ -550,20 +720,37 @@ struct Ops<CfgF32<A, B, Cc, D>> {
 template <int A, int B, int Cc, int D>
 struct Ops<CfgB3<A, B, Cc, D>> {
   using C = CfgB3<A, B, Cc, D>;
+  static constexpr int kSmem = 16;
   using T = typename C::T;
   __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc) {
+                              typename C::Acc& acc, char*) {
     mainloop_b3<C>(sc, w, acc);
   }
   // The BF16x3 accumulators have the FP32 32x32 layout.
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc) {
+                             const typename C::Acc& acc, char*) {
     epilogue_f32<C>(sc, part, slot, acc);
+  }
+};
+
+template <int A, int B, int Cc, int D>
+struct Ops<CfgB3S<A, B, Cc, D>> {
+  using C = CfgB3S<A, B, Cc, D>;
+  using T = typename C::T;
+  static constexpr int kSmem = C::SMEM;
+  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
+                              typename C::Acc& acc, char* smem) {
+    mainloop_b3s<C>(sc, w, acc, smem);
+  }
+  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
+                             const typename C::Acc& acc, char* smem) {
+    epilogue_lds_f32<C>(sc, part, slot, acc, smem);
   }
 };
 
 template <class C>
 __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
   const WorkItem w = a.items[blockIdx.x];
   if (w.slot < 0) return;
   const Instance& in = a.inst[w.inst];
@@ -571,9 +758,9 @@ __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   using T = typename C::T;
   const StepCtx<T> sc = step_ctx<T>(a, in, w.slot);
   typename C::Acc acc;
-  Ops<C>::main(sc, w, acc);
+  Ops<C>::main(sc, w, acc, smem);
   if (w.piece < 0) {
-    Ops<C>::epi(sc, a.part, w.slot, acc);
+    Ops<C>::epi(sc, a.part, w.slot, acc, smem);
   } else {
     ws_store<C>(acc, static_cast<T*>(a.ws) +
                          static_cast<size_t>(w.piece) * C::BM * C::BM);
@@ -583,6 +770,7 @@ __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
 // Sums the pieces of tail tile blockIdx.x in piece order, then the epilogue.
 template <class C>
 __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
+  __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
   const TailItem t = a.tails[blockIdx.x];
   const Instance& in = a.inst[t.inst];
   if (in.st->done) return;
@@ -594,7 +782,7 @@ __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   for (int j = 0; j < a.split; ++j)
     ws_accumulate<C>(acc, ws + static_cast<size_t>(t.piece0 + j) *
                                    C::BM * C::BM);
-  Ops<C>::epi(sc, a.part, t.slot, acc);
+  Ops<C>::epi(sc, a.part, t.slot, acc, smem);
 }
 
 // Kernel configurations: macro tile, waves (M x N), K slice.
@@ -607,6 +795,9 @@ using F32_256_2x2 = CfgF32<256, 2, 2, 16>;
 using B3_128_2x2 = CfgB3<128, 2, 2, 32>;
 using B3_256_2x2 = CfgB3<256, 2, 2, 16>;
 using B3_256_2x4 = CfgB3<256, 2, 4, 16>;
+using B3S_256_2x4 = CfgB3S<256, 2, 4, 32>;
+using B3S_256_2x4_16 = CfgB3S<256, 2, 4, 16>;
+using B3S_128_2x2 = CfgB3S<128, 2, 2, 32>;
 
 template <class C>
 hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
@@ -631,7 +822,8 @@ const KernelConfig kConfigs[] = {
     describe<F64_64_2x2>(0, 2),  describe<F32_128_2x2>(1, 2),
     describe<F32_128_2x4>(1, 1), describe<F32_256_2x2>(1, 1),
     describe<B3_128_2x2>(2, 1),  describe<B3_256_2x2>(2, 1),
-    describe<B3_256_2x4>(2, 1),
+    describe<B3_256_2x4>(2, 1),  describe<B3S_256_2x4>(2, 1),
+    describe<B3S_256_2x4_16>(2, 1), describe<B3S_128_2x2>(2, 2),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -654,6 +846,9 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 6: return launch_cfg<B3_128_2x2>(a, grid, s);
     case 7: return launch_cfg<B3_256_2x2>(a, grid, s);
     case 8: return launch_cfg<B3_256_2x4>(a, grid, s);
+    case 9: return launch_cfg<B3S_256_2x4>(a, grid, s);
+    case 10: return launch_cfg<B3S_256_2x4_16>(a, grid, s);
+    case 11: return launch_cfg<B3S_128_2x2>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -46,26 +46,22 @@ def main() -> int:
               f"{(statistics.median(lds) if lds else 0):.1f} | {min(ds):.1f} | {max(ds):.1f}")
     try:
         pmc = cur.execute(
-            "select p.event_id, i.name, p.value from rocpd_pmc_event p "
-            "join rocpd_info_pmc i on p.pmc_id = i.id").fetchall()
+            "select kernel_name, dispatch_id, counter_name, value, duration "
+            "from counters_collection").fetchall()
     except sqlite3.Error:
         pmc = []
     if pmc:
-        # map event ids to kernel dispatch ids
-        try:
-            ev2k = dict(cur.execute(
-                "select event_id, id from rocpd_kernel_dispatch").fetchall())
-        except sqlite3.Error:
-            ev2k = {}
-        print("\nkernel | counter | dispatches | mean per dispatch")
-        for name, ids in long_ids.items():
-            vals = {}
-            for ev, cname, v in pmc:
-                if ev2k.get(ev, ev) in ids:
-                    vals.setdefault(cname, []).append(v)
-            short = name if len(name) < 110 else name[:107] + "..."
-            for cname, vs in sorted(vals.items()):
-                print(f"{short} | {cname} | {len(vs)} | {statistics.mean(vs):.1f}")
+        print("\nkernel | counter | long dispatches | mean value per dispatch")
+        vals = {}
+        for kname, _did, cname, v, dur in pmc:
+            if args.match and args.match not in kname and "copyBuffer" not in kname:
+                continue
+            if dur is not None and dur / 1e3 <= args.min_us and "copyBuffer" not in kname:
+                continue
+            vals.setdefault((kname, cname), []).append(v)
+        for (kname, cname), vs in sorted(vals.items()):
+            short = kname if len(kname) < 110 else kname[:107] + "..."
+            print(f"{short} | {cname} | {len(vs)} | {statistics.mean(vs):.6g}")
     return 0
 
 
