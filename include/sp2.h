@@ -286,6 +286,12 @@ sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
                                   int32_t* tile, int32_t* waves_m,
                                   int32_t* waves_n, int32_t* k_slice);
 
+/* Name of configuration `id` (1-based): kernel family (F64, F32, B3 padded
+ * LDS, B3S swizzled LDS, B3P pre-split operands), macro tile, waves and, where
+ * it is not the family's default, the K slice, e.g. "B3P_256_2x4_32". A
+ * static string; NULL for an unknown id. */
+const char* sp2_kernel_config_name(int32_t id);
+
 /* Static description of a status code. */
 const char* sp2_status_string(sp2_status s);
 

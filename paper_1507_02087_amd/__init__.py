@@ -67,6 +67,7 @@ SIGNATURES = {
                                         _c.c_void_p]),
     "sp2_kernel_config_count": (_c.c_int32, []),
     "sp2_kernel_config_info": (_c.c_int, [_c.c_int32] + [_c.POINTER(_c.c_int32)] * 5),
+    "sp2_kernel_config_name": (_c.c_char_p, [_c.c_int32]),
     "sp2_status_string": (_c.c_char_p, [_c.c_int]),
     "sp2_last_error": (_c.c_char_p, [_c.c_void_p]),
 }
@@ -179,13 +180,11 @@ class Context:
         path = path or TABLE_PATH
         with open(path) as fh:
             data = json.load(fh)
-        ids = {(c["precision"], c["tile"], c["waves_m"], c["waves_n"], c["k_slice"]): c["id"]
-               for c in kernel_configs()}
+        ids = {c["name"]: c["id"] for c in kernel_configs()}
         entries = []
         for e in data["entries"]:
-            key = (e["precision"], e["tile"], e["waves_m"], e["waves_n"], e["k_slice"])
-            if key in ids:
-                entries.append((e["precision"], e["n_max"], ids[key]))
+            if e["name"] in ids:
+                entries.append((e["precision"], e["n_max"], ids[e["name"]]))
         self.set_kernel_table(entries)
         return entries
 
@@ -479,6 +478,7 @@ def kernel_configs():
         if st != OK:
             raise SP2Error(st, "sp2_kernel_config_info")
         prec, tile, wm, wn, bk = (v.value for v in vals)
-        out.append(dict(id=i, precision=names[prec], tile=tile, waves_m=wm,
+        out.append(dict(id=i, name=lib.sp2_kernel_config_name(i).decode(),
+                        precision=names[prec], tile=tile, waves_m=wm,
                         waves_n=wn, k_slice=bk))
     return out

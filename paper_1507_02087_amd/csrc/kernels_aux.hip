@@ -79,6 +79,8 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   const int n_occ = static_cast<int>(in.prm.n_occ);
   const int trivial = (n_occ == 0) ? 1 : (n_occ == n ? 2 : 0);
   T* X = static_cast<T*>(in.X[0]);
+  __bf16* XH = static_cast<__bf16*>(in.XH[0]);
+  __bf16* XL = static_cast<__bf16*>(in.XL[0]);
   double t1 = 0.0, t2 = 0.0;
   for (int rr = 0; rr < kF0Rows; ++rr) {
     const int i = it.row0 + rr;
@@ -98,6 +100,13 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
       const T xs = static_cast<T>(x);
       const double xd = static_cast<double>(xs);
       Xi[j] = xs;
+      if (XH) {
+        const float xf = static_cast<float>(xs);
+        const __bf16 hb = static_cast<__bf16>(xf);
+        const size_t o = static_cast<size_t>(i) * np + j;
+        XH[o] = hb;
+        XL[o] = static_cast<__bf16>(xf - static_cast<float>(hb));
+      }
       t2 += xd * xd;
       if (i == j) t1 += xd;
     }

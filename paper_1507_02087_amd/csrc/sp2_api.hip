@@ -91,6 +91,8 @@ struct sp2_ctx_s {
   // device workspaces
   void* pool[2] = {nullptr, nullptr};
   size_t pool_cap[2] = {0, 0};
+  void* split_pool[4] = {nullptr, nullptr, nullptr, nullptr};   // H0 L0 H1 L1
+  size_t split_cap[4] = {0, 0, 0, 0};
   Instance* d_inst = nullptr;
   size_t d_inst_cap = 0;
   DevState* d_st = nullptr;
@@ -170,7 +172,7 @@ int default_config(int precision, int64_t n) {
   switch (precision) {
     case SP2_FP64: return n >= 1024 ? 0 : 2;
     case SP2_FP32: return n >= 1024 ? 4 : 3;
-    default: return n >= 6144 ? 9 : 11;
+    default: return n >= 6144 ? 13 : 11;
   }
 }
 
@@ -334,6 +336,10 @@ sp2_status setup(sp2_ctx c) {
   }
   for (int q = 0; q < 2; ++q)
     SP2_HIP(c, grow(c->pool[q], c->pool_cap[q], pool_elems * esz, s));
+  const bool split = (c->opt.precision == SP2_BF16X3);
+  if (split)
+    for (int q = 0; q < 4; ++q)
+      SP2_HIP(c, grow(c->split_pool[q], c->split_cap[q], pool_elems * 2, s));
 
   // instance table, tiles and affine-start blocks
   SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
@@ -346,6 +352,12 @@ sp2_status setup(sp2_ctx c) {
     Instance& in = inst[b];
     in.X[0] = static_cast<char*>(c->pool[0]) + h.xoff * esz;
     in.X[1] = static_cast<char*>(c->pool[1]) + h.xoff * esz;
+    for (int q = 0; q < 2; ++q) {
+      in.XH[q] = split ? static_cast<char*>(c->split_pool[2 * q]) + h.xoff * 2
+                       : nullptr;
+      in.XL[q] = split ? static_cast<char*>(c->split_pool[2 * q + 1]) + h.xoff * 2
+                       : nullptr;
+    }
     in.F = h.F;
     in.ldf = h.ldf;
     in.n = static_cast<int>(h.n);
@@ -670,6 +682,11 @@ sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
   return SP2_OK;
 }
 
+const char* sp2_kernel_config_name(int32_t id) {
+  const sp2::KernelConfig* k = sp2::kernel_config(id - 1);
+  return k ? k->name : nullptr;
+}
+
 sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream) {
   if (!out) return SP2_INVALID_ARG;
   *out = nullptr;
@@ -711,6 +728,7 @@ sp2_status sp2_destroy(sp2_ctx c) {
   };
   rel(c->pool[0]);
   rel(c->pool[1]);
+  for (void* p : c->split_pool) rel(p);
   rel(c->d_inst);
   rel(c->d_st);
   rel(c->d_tiles);

@@ -69,6 +69,11 @@ struct StopParams {
 // One instance as the kernels see it.
 struct Instance {
   void* X[2];          // iterate buffers (step i reads X[(i-1)&1])
+  // BF16x3 only: the iterate split as H = bf16(x), L = bf16(x - H), same
+  // layout as X, written by the affine start and by the epilogues of the
+  // kernel families that read them (null otherwise)
+  void* XH[2];
+  void* XL[2];
   const double* F;     // input, FP64, row-major
   int64_t ldf;
   int n;               // matrix dimension
@@ -116,6 +121,7 @@ struct KernelConfig {
   int bk;          // K slice staged per LDS buffer
   int threads;     // workgroup size
   int occupancy;   // workgroups per CU the configuration is built for
+  const char* name;  // family, tile, waves and K slice, e.g. "B3P_256_2x4_32"
 };
 
 // Arguments of one square step of one launch group (instances sharing a

@@ -146,6 +146,10 @@ template <typename T>
 struct StepCtx {
   const T* X;     // X~_{i-1}
   T* Y;           // X~_i
+  const __bf16* Xh;   // BF16x3 split of X~_{i-1} (null if absent)
+  const __bf16* Xl;
+  __bf16* Yh;         // BF16x3 split of X~_i (null if absent)
+  __bf16* Yl;
   int ld;
   int2 tile;      // (I, J)
   int p;          // polynomial of step i
@@ -158,6 +162,10 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
   StepCtx<T> c;
   c.X = static_cast<const T*>(in.X[(a.iter - 1) & 1]);
   c.Y = static_cast<T*>(in.X[a.iter & 1]);
+  c.Xh = static_cast<const __bf16*>(in.XH[(a.iter - 1) & 1]);
+  c.Xl = static_cast<const __bf16*>(in.XL[(a.iter - 1) & 1]);
+  c.Yh = static_cast<__bf16*>(in.XH[a.iter & 1]);
+  c.Yl = static_cast<__bf16*>(in.XL[a.iter & 1]);
   c.ld = in.ld;
   c.tile = a.tiles[slot];
   c.p = in.st->p[a.iter];
@@ -591,6 +599,135 @@ __device__ __forceinline__ void mainloop_b3s(const StepCtx<float>& sc,
   }
 }
 
+// Stores the BF16x3 split of x: H = bf16(x), L = bf16(x - H).
+__device__ __forceinline__ void store_split(__bf16* Yh, __bf16* Yl, size_t i,
+                                            float x) {
+  const __bf16 hb = static_cast<__bf16>(x);
+  *grw(Yh + i) = hb;
+  *grw(Yl + i) = static_cast<__bf16>(x - static_cast<float>(hb));
+}
+
+// ============================================================== BF16x3, v3
+// Same arithmetic and LDS layout as v2, but the operands arrive already
+// split: the affine start and the v2/v3 epilogues store H = bf16(x) and
+// L = bf16(x - H) beside the FP32 iterate, so the K loop moves bf16 chunks
+// from global memory to LDS with no conversion. Global loads run two K
+// slices ahead (two register sets, loop unrolled by two).
+template <int BM_, int WM_, int WN_, int BK_>
+struct CfgB3P : CfgB3S<BM_, WM_, WN_, BK_> {};
+
+template <class C>
+struct SplitStage {
+  static constexpr int CPR = C::BK / 8;                  // 16-B chunks per row
+  static constexpr int NC = C::BM * CPR / C::THREADS;    // chunks per thread
+  static_assert(C::BM * CPR % C::THREADS == 0, "stage size");
+  bf16x8 ah[NC], al[NC], bh[NC], bl[NC];
+  __device__ __forceinline__ static int row(int tid, int q) {
+    return (tid + q * C::THREADS) / CPR;
+  }
+  __device__ __forceinline__ static int col(int tid, int q) {
+    return ((tid + q * C::THREADS) % CPR) * 8;
+  }
+  __device__ __forceinline__ void load(const __bf16* Ah, const __bf16* Al,
+                                       const __bf16* Bh, const __bf16* Bl,
+                                       int ld, int k0, int tid) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const size_t off = static_cast<size_t>(row(tid, q)) * ld + k0 + col(tid, q);
+      ah[q] = *gro(reinterpret_cast<const bf16x8*>(Ah + off));
+      al[q] = *gro(reinterpret_cast<const bf16x8*>(Al + off));
+      bh[q] = *gro(reinterpret_cast<const bf16x8*>(Bh + off));
+      bl[q] = *gro(reinterpret_cast<const bf16x8*>(Bl + off));
+    }
+  }
+};
+
+template <class C>
+__device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
+                                             const WorkItem& w,
+                                             typename C::Acc& acc,
+                                             char* smem) {
+  __bf16* lds = reinterpret_cast<__bf16*>(smem);
+  auto arr = [&](int b, int a) { return lds + (b * 4 + a) * C::ARR; };
+  const int2 tt = sc.tile;
+  const int ld = sc.ld;
+  const size_t ao = static_cast<size_t>(tt.x * C::BM) * ld;
+  const size_t bo = static_cast<size_t>(tt.y * C::BM) * ld;
+  const __bf16 *Ah = sc.Xh + ao, *Al = sc.Xl + ao;
+  const __bf16 *Bh = sc.Xh + bo, *Bl = sc.Xl + bo;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  const int r = lane & 31, h = lane >> 5;
+  using St = SplitStage<C>;
+  St s0, s1;
+  auto sstore = [&](const St& st, int b) {
+#pragma unroll
+    for (int q = 0; q < St::NC; ++q) {
+      const int o = swz_off<C::BK>(St::row(tid, q), St::col(tid, q));
+      *reinterpret_cast<bf16x8*>(arr(b, 0) + o) = st.ah[q];
+      *reinterpret_cast<bf16x8*>(arr(b, 1) + o) = st.al[q];
+      *reinterpret_cast<bf16x8*>(arr(b, 2) + o) = st.bh[q];
+      *reinterpret_cast<bf16x8*>(arr(b, 3) + o) = st.bl[q];
+    }
+  };
+  auto compute = [&](int b) {
+#pragma unroll
+    for (int s8 = 0; s8 < C::KH; s8 += 8) {
+      bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m) {
+        const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
+        ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
+        al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
+      }
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n) {
+        const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
+        bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
+        bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
+      }
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n)
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bh[n], acc.c[m][n], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n)
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              ah[m], bl[n], acc.c[m][n], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+        for (int n = 0; n < C::NB; ++n)
+          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+              al[m], bh[n], acc.c[m][n], 0, 0, 0);
+    }
+  };
+  acc_zero<C>(acc);
+  const int k0 = w.k0, k1 = w.k1;
+  s0.load(Ah, Al, Bh, Bl, ld, k0 * C::BK, tid);
+  sstore(s0, 0);
+  if (k0 + 1 < k1) s0.load(Ah, Al, Bh, Bl, ld, (k0 + 1) * C::BK, tid);
+  if (k0 + 2 < k1) s1.load(Ah, Al, Bh, Bl, ld, (k0 + 2) * C::BK, tid);
+  __syncthreads();
+  // one K slice: compute slice kt from LDS buffer b, store slice kt + 1
+  // (held in st) into the other buffer, refill st with slice kt + 3
+  auto step = [&](int kt, St& st) {
+    const int b = (kt - k0) & 1;
+    compute(b);
+    if (kt + 1 < k1) sstore(st, b ^ 1);
+    if (kt + 3 < k1) st.load(Ah, Al, Bh, Bl, ld, (kt + 3) * C::BK, tid);
+    __syncthreads();
+  };
+  for (int kt = k0; kt < k1; kt += 2) {
+    step(kt, s0);
+    if (kt + 1 < k1) step(kt + 1, s1);
+  }
+}
+
 // Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
 // (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
 // The tile is processed one band of TM rows at a time (the rows of one row
@@ -612,6 +749,7 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
   const int ld = sc.ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = wave / C::WN, wn = (wave % C::WN) * C::TN;
+  const bool split = (sc.Yh != nullptr);
   Sums sums;
   for (int g = 0; g < C::WM; ++g) {
     __syncthreads();
@@ -638,6 +776,7 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx), sc.p,
                                     sc.tau, on ? 1.0 : 2.0, on, sums);
       *grw(sc.Y + idx) = xn;
+      if (split) store_split(sc.Yh, sc.Yl, idx, xn);
       S[rr * LD + cc] = xn;
     }
     __syncthreads();
@@ -645,7 +784,10 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       const int cc = e / TM, rr = e % TM;
       const int gr = r0 + rr, gc = J * BM + cc;
       if (diag && gr >= gc) continue;
-      *grw(sc.Y + static_cast<size_t>(gc) * ld + gr) = S[rr * LD + cc];
+      const size_t idt = static_cast<size_t>(gc) * ld + gr;
+      const T xn = S[rr * LD + cc];
+      *grw(sc.Y + idt) = xn;
+      if (split) store_split(sc.Yh, sc.Yl, idt, xn);
     }
   }
   store_partials<C::THREADS>(sums, part, slot);
@@ -748,6 +890,21 @@ struct Ops<CfgB3S<A, B, Cc, D>> {
   }
 };
 
+template <int A, int B, int Cc, int D>
+struct Ops<CfgB3P<A, B, Cc, D>> {
+  using C = CfgB3P<A, B, Cc, D>;
+  using T = typename C::T;
+  static constexpr int kSmem = C::SMEM;
+  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
+                              typename C::Acc& acc, char* smem) {
+    mainloop_b3p<C>(sc, w, acc, smem);
+  }
+  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
+                             const typename C::Acc& acc, char* smem) {
+    epilogue_lds_f32<C>(sc, part, slot, acc, smem);
+  }
+};
+
 template <class C>
 __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
@@ -798,6 +955,9 @@ using B3_256_2x4 = CfgB3<256, 2, 4, 16>;
 using B3S_256_2x4 = CfgB3S<256, 2, 4, 32>;
 using B3S_256_2x4_16 = CfgB3S<256, 2, 4, 16>;
 using B3S_128_2x2 = CfgB3S<128, 2, 2, 32>;
+using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
+using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
+using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
 
 template <class C>
 hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
@@ -810,20 +970,24 @@ hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
 }
 
 template <class C>
-constexpr KernelConfig describe(int precision, int occupancy) {
+constexpr KernelConfig describe(int precision, int occupancy,
+                                const char* name) {
   return KernelConfig{precision, C::BM, C::WM, C::WN, C::BK, C::THREADS,
-                      occupancy};
+                      occupancy, name};
 }
+#define SP2_DESCRIBE(C, prec, occ) describe<C>(prec, occ, #C)
 
 // Occupancy = workgroups per CU that the configuration's LDS and registers
 // allow; the host uses it to size the split of tail tiles.
 const KernelConfig kConfigs[] = {
-    describe<F64_128_2x4>(0, 1), describe<F64_128_2x2>(0, 1),
-    describe<F64_64_2x2>(0, 2),  describe<F32_128_2x2>(1, 2),
-    describe<F32_128_2x4>(1, 1), describe<F32_256_2x2>(1, 1),
-    describe<B3_128_2x2>(2, 1),  describe<B3_256_2x2>(2, 1),
-    describe<B3_256_2x4>(2, 1),  describe<B3S_256_2x4>(2, 1),
-    describe<B3S_256_2x4_16>(2, 1), describe<B3S_128_2x2>(2, 2),
+    SP2_DESCRIBE(F64_128_2x4, 0, 1), SP2_DESCRIBE(F64_128_2x2, 0, 1),
+    SP2_DESCRIBE(F64_64_2x2, 0, 2),  SP2_DESCRIBE(F32_128_2x2, 1, 2),
+    SP2_DESCRIBE(F32_128_2x4, 1, 1), SP2_DESCRIBE(F32_256_2x2, 1, 1),
+    SP2_DESCRIBE(B3_128_2x2, 2, 1),  SP2_DESCRIBE(B3_256_2x2, 2, 1),
+    SP2_DESCRIBE(B3_256_2x4, 2, 1),  SP2_DESCRIBE(B3S_256_2x4, 2, 1),
+    SP2_DESCRIBE(B3S_256_2x4_16, 2, 1), SP2_DESCRIBE(B3S_128_2x2, 2, 2),
+    SP2_DESCRIBE(B3P_256_2x4, 2, 1), SP2_DESCRIBE(B3P_256_2x4_32, 2, 1),
+    SP2_DESCRIBE(B3P_128_2x2, 2, 2),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -849,6 +1013,9 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 9: return launch_cfg<B3S_256_2x4>(a, grid, s);
     case 10: return launch_cfg<B3S_256_2x4_16>(a, grid, s);
     case 11: return launch_cfg<B3S_128_2x2>(a, grid, s);
+    case 12: return launch_cfg<B3P_256_2x4>(a, grid, s);
+    case 13: return launch_cfg<B3P_256_2x4_32>(a, grid, s);
+    case 14: return launch_cfg<B3P_128_2x2>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -57,7 +57,15 @@ def test_default_options_and_kernel_configs():
     assert {c["precision"] for c in cfgs} == {"fp64", "fp32", "bf16x3"}
     for c in cfgs:
         assert c["tile"] % (16 * c["waves_m"]) == 0 and c["tile"] % (16 * c["waves_n"]) == 0
+    names = [c["name"] for c in cfgs]
+    assert len(set(names)) == len(names)
+    for c in cfgs:   # the name carries the family's precision, tile and waves
+        fam, tile, waves = c["name"].split("_")[:3]
+        assert {"F64": "fp64", "F32": "fp32"}.get(fam, "bf16x3") == c["precision"]
+        assert (int(tile), waves) == (c["tile"], f"{c['waves_m']}x{c['waves_n']}")
     lib = sp2.load_library()
+    assert lib.sp2_kernel_config_name(0) is None
+    assert lib.sp2_kernel_config_name(len(cfgs) + 1) is None
     assert lib.sp2_kernel_config_info(0, None, None, None, None, None) == sp2.INVALID_ARG
     assert lib.sp2_kernel_config_info(len(cfgs) + 1, None, None, None, None, None) == sp2.INVALID_ARG
 
