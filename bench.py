@@ -31,6 +31,33 @@ PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PRODUCTS = {"bf16x3": 3, "fp32": 1, "fp64": 1}
 
 
+KERNEL_SOURCE = os.path.join("paper_1507_02087_amd", "csrc", "square_dense.hip")
+
+
+def measured_traffic(config_name: str):
+    """HBM bytes per square step (main + tail kernel) of configuration
+    `config_name`, from the TRAFFIC line of a committed PMC summary under
+    profiles/ (two rocprofv3 passes, FETCH_SIZE and WRITE_SIZE, each scaled by
+    a plain copy of known size). Returned only while the kernel source still
+    hashes to the value recorded with the counters; otherwise None."""
+    import glob
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, KERNEL_SOURCE), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None, None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("TRAFFIC "):
+                    continue
+                rec = json.loads(line[len("TRAFFIC "):])
+                if rec.get("config") == config_name and rec.get("source_sha256") == sha:
+                    return rec["bytes_per_step"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -337,6 +364,8 @@ def main() -> int:
     flops = square_flops(n)
     exec_flops = flops * PRODUCTS[prec]
     achieved = exec_flops / (avg_sq_ms * 1e-3) / 1e12
+    cfg_id, cfg_name = ctx.get_config(0)
+    traffic, traffic_src = measured_traffic(cfg_name)
     out = {
         "metric": METRIC,
         "value": round(float(np.median(dev_ms)), 3),
@@ -369,9 +398,10 @@ def main() -> int:
             "peak": PEAK_TFLOPS[prec],
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS[prec], 4),
-            "traffic": None,
-            "kernel": f"square_{prec}",
+            "traffic": traffic,
+            "kernel": f"square_{prec} ({cfg_name}: main + tail kernel per square)",
             "per_launch_flops": exec_flops,
+            "traffic_source": traffic_src,
         },
     }
 

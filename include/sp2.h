@@ -292,6 +292,14 @@ sp2_status sp2_kernel_config_info(int32_t id, int32_t* precision,
  * static string; NULL for an unknown id. */
 const char* sp2_kernel_config_name(int32_t id);
 
+/* The square-kernel configuration (1-based id) that instance `index` of the
+ * last sp2_init_dense / sp2_batch_init uses (index 0 for a dense context),
+ * as chosen by options.kernel_config, the context's kernel table or the
+ * built-in default, in that order. *config_id = 0 for an instance with
+ * n_occ = 0 or n (no square is computed) and for block-sparse contexts.
+ * Errors: SP2_BAD_STATE before an init, SP2_INVALID_ARG. */
+sp2_status sp2_get_config(sp2_ctx ctx, int32_t index, int32_t* config_id);
+
 /* Static description of a status code. */
 const char* sp2_status_string(sp2_status s);
 

@@ -61,6 +61,7 @@ SIGNATURES = {
                                          _c.POINTER(_c.c_int32), _c.c_void_p,
                                          _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                          _c.c_void_p]),
+    "sp2_get_config": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32)]),
     "sp2_batch_get_run_time": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double),
                                           _c.POINTER(_c.c_int32)]),
     "sp2_set_kernel_table": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
@@ -259,6 +260,16 @@ class Context:
         self._check(self._lib.sp2_get_info(self._h, ctypes.byref(n), ctypes.byref(sq),
                                            ctypes.byref(ms)), "sp2_get_info")
         return n.value, sq.value, ms.value
+
+    def get_config(self, index: int = 0):
+        """(id, name) of the square-kernel configuration instance `index`
+        uses; (0, None) where no square is computed."""
+        cid = ctypes.c_int32()
+        self._check(self._lib.sp2_get_config(self._h, index, ctypes.byref(cid)),
+                    "sp2_get_config")
+        if cid.value == 0:
+            return 0, None
+        return cid.value, self._lib.sp2_kernel_config_name(cid.value).decode()
 
     def get_kernel_times(self):
         """Square-kernel durations (ms) of the last run with kernel_timing."""

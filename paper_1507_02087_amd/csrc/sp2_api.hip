@@ -1088,6 +1088,16 @@ sp2_status sp2_get_info(sp2_ctx c, int32_t* n_iter, int32_t* n_squares,
   return SP2_OK;
 }
 
+sp2_status sp2_get_config(sp2_ctx c, int32_t index, int32_t* config_id) {
+  if (!c || !config_id) return SP2_INVALID_ARG;
+  if (!c->inited) return SP2_BAD_STATE;
+  if (index < 0 || index >= static_cast<int32_t>(c->hi.size()))
+    return SP2_INVALID_ARG;
+  const HostInst& h = c->hi[index];
+  *config_id = (c->bsr || h.trivial) ? 0 : h.cfg + 1;
+  return SP2_OK;
+}
+
 sp2_status sp2_batch_get_run_time(sp2_ctx c, double* run_ms, int32_t* steps) {
   if (!c) return SP2_INVALID_ARG;
   if (!c->ran) return SP2_BAD_STATE;

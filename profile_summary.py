@@ -2,12 +2,22 @@
 PMC counters) as short text for profiles/.
 
 Usage: python profile_summary.py <results.db> [--min-us 20] [--match square]
+       python profile_summary.py <fetch.db> --write-db <write.db> --match square
+              --copy-bytes 1073741824 --source <kernel source> --config <name>
 
 Per kernel it prints the dispatch count and mean duration over all
 dispatches, and over the dispatches longer than --min-us (kernels of steps
 queued after the stop return at once; they are excluded from the second
 mean). With counters, it prints the per-dispatch mean of each counter over
 the same long dispatches.
+
+Traffic mode (--write-db): the first database holds a FETCH_SIZE pass and the
+second a WRITE_SIZE pass of the same command, which ends with plain device
+copies of --copy-bytes bytes. Each counter is scaled by the copy's known bytes
+over what the counter reads for the copy; the scaled fetch and write bytes of
+the matching kernels (main and tail kernel of one step) are summed per step
+and printed as one TRAFFIC line with the SHA-256 of the kernel source, so a
+reader can tell whether the figure still describes the current kernel.
 """
 from __future__ import annotations
 
@@ -22,7 +32,13 @@ def main() -> int:
     ap.add_argument("db")
     ap.add_argument("--min-us", type=float, default=20.0)
     ap.add_argument("--match", default="")
+    ap.add_argument("--write-db", default=None)
+    ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    ap.add_argument("--source", default=None)
+    ap.add_argument("--config", default=None)
     args = ap.parse_args()
+    if args.write_db:
+        return traffic(args)
     con = sqlite3.connect(args.db)
     cur = con.cursor()
     rows = cur.execute("select id, name, duration from kernels").fetchall()
@@ -62,6 +78,67 @@ def main() -> int:
         for (kname, cname), vs in sorted(vals.items()):
             short = kname if len(kname) < 110 else kname[:107] + "..."
             print(f"{short} | {cname} | {len(vs)} | {statistics.mean(vs):.6g}")
+    return 0
+
+
+def _counter_means(db, counter, match, min_us, copy_bytes):
+    """Mean KiB per long dispatch of each matching kernel, and the counter's
+    KiB for the calibration copies (dispatches of the copy kernel reading
+    at least a quarter of copy_bytes)."""
+    cur = sqlite3.connect(db).cursor()
+    rows = cur.execute("select kernel_name, value, duration from counters_collection "
+                       "where counter_name = ?", (counter,)).fetchall()
+    per, copies = {}, []
+    for kname, v, dur in rows:
+        if "copyBuffer" in kname:
+            if v * 1024.0 >= 0.25 * copy_bytes:
+                copies.append(v)
+            continue
+        if match and match not in kname:
+            continue
+        if dur is not None and dur / 1e3 <= min_us:
+            continue
+        per.setdefault(kname, []).append(v)
+    return {k: statistics.mean(v) for k, v in per.items()}, per, copies
+
+
+def traffic(args) -> int:
+    import hashlib
+    import json
+    fetch, fper, fcopy = _counter_means(args.db, "FETCH_SIZE", args.match,
+                                        args.min_us, args.copy_bytes)
+    write, wper, wcopy = _counter_means(args.write_db, "WRITE_SIZE", args.match,
+                                        args.min_us, args.copy_bytes)
+    if not fcopy or not wcopy:
+        print("no calibration copy found in the databases", file=sys.stderr)
+        return 1
+    ff = args.copy_bytes / (statistics.mean(fcopy) * 1024.0)
+    wf = args.copy_bytes / (statistics.mean(wcopy) * 1024.0)
+    print(f"# traffic from {args.db} (FETCH_SIZE) and {args.write_db} (WRITE_SIZE)")
+    print(f"# calibration: copies of {args.copy_bytes:.0f} B read as FETCH_SIZE "
+          f"{statistics.mean(fcopy):.1f} KiB (x{ff:.3f}) and WRITE_SIZE "
+          f"{statistics.mean(wcopy):.1f} KiB (x{wf:.3f}), {len(fcopy)}/{len(wcopy)} copies")
+    print("kernel | long dispatches (fetch/write) | FETCH_SIZE KiB | WRITE_SIZE KiB | "
+          "scaled read GB | scaled write GB")
+    tot_r = tot_w = 0.0
+    names = sorted(set(fetch) | set(write))
+    for k in names:
+        r = fetch.get(k, 0.0) * 1024.0 * ff
+        w = write.get(k, 0.0) * 1024.0 * wf
+        tot_r += r
+        tot_w += w
+        short = k if len(k) < 110 else k[:107] + "..."
+        print(f"{short} | {len(fper.get(k, []))}/{len(wper.get(k, []))} | "
+              f"{fetch.get(k, 0.0):.1f} | {write.get(k, 0.0):.1f} | "
+              f"{r / 1e9:.4f} | {w / 1e9:.4f}")
+    rec = {"config": args.config, "kernels": names, "read_bytes": round(tot_r),
+           "write_bytes": round(tot_w), "bytes_per_step": round(tot_r + tot_w),
+           "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)}
+    if args.source:
+        with open(args.source, "rb") as fh:
+            rec["source"] = args.source
+            rec["source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+    print("TRAFFIC " + json.dumps(rec))
     return 0
 
 
