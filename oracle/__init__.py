@@ -5,7 +5,8 @@ smoke check and by the CPU-baseline leg of the benchmark, never by the
 library or its Python binding. It shares no code with the GPU path: it is a
 plain, slow, step-by-step restatement of the paper's algorithm in NumPy
 float64 (Kruchinina, Rudberg, Rubensson, "Parameterless stopping criteria
-for recursive density matrix expansions", Alg. 2 and sec. 2).
+for recursive density matrix expansions", Alg. 2 and sec. 2; SP2-ACC,
+Alg. 3 and Alg. 4).
 """
 from .sp2 import (  # noqa: F401
     C_SP2,
@@ -23,4 +24,13 @@ from .sp2 import (  # noqa: F401
     g_ratio,
     p_sp1,
     p_sp2,
+)
+from .sp2acc import (  # noqa: F401
+    EPS_M,
+    DELTA,
+    Schedule,
+    bounds_valid,
+    acc_schedule,
+    acc_polynomial,
+    sp2_acc,
 )
