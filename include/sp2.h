@@ -263,6 +263,60 @@ sp2_status sp2_batch_get_history(sp2_ctx ctx, int32_t idx, int32_t cap,
 sp2_status sp2_batch_get_run_time(sp2_ctx ctx, double* run_ms,
                                   int32_t* steps);
 
+/* ---------------------------------------------------------------------
+ * SP2-ACC: a polynomial schedule from homo/lumo bounds with scale-and-fold
+ * acceleration (Alg. 3 and Alg. 4 of the paper, sec. 4).
+ *
+ * Given lambda_min <= homo_out <= homo_in < lumo_in <= lumo_out <=
+ * lambda_max (homo_out/homo_in bound the highest occupied eigenvalue of F
+ * from below/above, lumo_in/lumo_out the lowest unoccupied one), Alg. 3
+ * fixes before the run, for every step i = 1..n_max, the polynomial p_i and
+ * the stretch alpha_i >= 1:
+ *   X_i = ((1 - alpha_i) I + alpha_i X~_{i-1})^2        (p_i = 1)
+ *       = 2 alpha_i X~_{i-1} - (alpha_i X~_{i-1})^2     (p_i = 0)
+ * The stretch is switched off (alpha = 1) once both outer-bound distances
+ * are below 0.01; the stop test of Alg. 2 is evaluated from step n_min on
+ * (instead of 2). Readings fixed here:
+ *   - the loop of Alg. 3 runs while the bounds are not idempotent to the
+ *     FP64 machine epsilon or the last two polynomials are equal (so the
+ *     schedule ends on an alternation); it has at least two steps;
+ *   - if the stop has not fired at step n_max, X~_{n_max} is returned with
+ *     n = n_max and SP2_OK;
+ *   - homo_in > lambda_min and lumo_in < lambda_max are required.
+ * Each step still computes one square S = X~_{i-1}^2 and forms
+ * X_i = a S + b X~_{i-1} + c I in the square's epilogue with
+ * (a, b, c) = (alpha^2, 2 alpha (1 - alpha), (1 - alpha)^2) for p_i = 1 and
+ * (-alpha^2, 2 alpha, 0) for p_i = 0.
+ * --------------------------------------------------------------------- */
+
+/* Alg. 3 alone, on the host (no device, no context). accelerate = 0 uses
+ * the lower bounds 0 (alpha_i = 1, the setting of Theorem 2). Writes n_min
+ * and n_max, and p[i-1], alpha[i-1] for i = 1..n_max when the arrays are
+ * given (host arrays of cap entries; either may be NULL; with both NULL cap
+ * is ignored). Errors: SP2_INVALID_ARG for bounds that are not finite, out
+ * of order or overlapping, for NULL n_min/n_max, or when the schedule needs
+ * more than cap (or SP2_MAX_ITER_LIMIT) steps. */
+sp2_status sp2_acc_schedule(double lambda_min, double lambda_max,
+                            double homo_out, double homo_in, double lumo_in,
+                            double lumo_out, int32_t accelerate, int32_t cap,
+                            int32_t* n_min, int32_t* n_max, int8_t* p,
+                            double* alpha);
+
+/* Switches the instances of the last sp2_init_dense, sp2_init_bsr or
+ * sp2_batch_init to SP2-ACC (Alg. 4) for the following runs: count must
+ * equal the number of instances (1 for dense and block-sparse contexts);
+ * the four host arrays give each instance's bounds, with the lambda_min and
+ * lambda_max of its init. The schedule replaces opt->branch; opt->max_iter
+ * still caps the squares (a schedule needs up to n_max + 1). A later init
+ * returns the context to Alg. 2. Errors: SP2_BAD_STATE before an init,
+ * SP2_INVALID_ARG (count mismatch, NULL arrays, or bounds of an instance
+ * that sp2_acc_schedule rejects; the message names the instance),
+ * SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. */
+sp2_status sp2_set_homo_lumo(sp2_ctx ctx, int32_t count,
+                             const double* homo_out, const double* homo_in,
+                             const double* lumo_in, const double* lumo_out,
+                             int32_t accelerate);
+
 /* Installs a table that chooses the square-kernel configuration per
  * instance when opt->kernel_config is 0: for an instance of dimension n and
  * precision p, the first entry e (in the given order) with precision[e] == p

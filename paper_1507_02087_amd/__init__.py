@@ -62,6 +62,12 @@ SIGNATURES = {
                                          _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                          _c.c_void_p]),
     "sp2_get_config": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32)]),
+    "sp2_acc_schedule": (_c.c_int, [_c.c_double] * 6 + [_c.c_int32, _c.c_int32,
+                                                      _c.POINTER(_c.c_int32),
+                                                      _c.POINTER(_c.c_int32),
+                                                      _c.c_void_p, _c.c_void_p]),
+    "sp2_set_homo_lumo": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                                     _c.c_void_p, _c.c_void_p, _c.c_int32]),
     "sp2_batch_get_run_time": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double),
                                           _c.POINTER(_c.c_int32)]),
     "sp2_set_kernel_table": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
@@ -261,6 +267,22 @@ class Context:
                                            ctypes.byref(ms)), "sp2_get_info")
         return n.value, sq.value, ms.value
 
+    def set_homo_lumo(self, homo_out, homo_in, lumo_in, lumo_out,
+                      accelerate: bool = True):
+        """Switches the instances of the last init to SP2-ACC (Alg. 3/4):
+        scalars for a dense or block-sparse context, sequences (one entry per
+        instance) for a batch."""
+        vals = [homo_out, homo_in, lumo_in, lumo_out]
+        if all(isinstance(v, (int, float)) for v in vals):
+            vals = [[v] for v in vals]
+        cnt = len(vals[0])
+        if any(len(v) != cnt for v in vals):
+            raise ValueError("bound sequences differ in length")
+        arrs = [_arr(ctypes.c_double, [float(x) for x in v]) for v in vals]
+        self._check(self._lib.sp2_set_homo_lumo(self._h, cnt, *arrs,
+                                                1 if accelerate else 0),
+                    "sp2_set_homo_lumo")
+
     def get_config(self, index: int = 0):
         """(id, name) of the square-kernel configuration instance `index`
         uses; (0, None) where no square is computed."""
@@ -431,13 +453,17 @@ class BatchContext(Context):
 
 
 def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None,
-              as_fp64: bool = True, **opts):
-    """SP2 on many independent matrices at once; returns (results, run_ms)."""
+              as_fp64: bool = True, homo_lumo=None, accelerate: bool = True, **opts):
+    """SP2 on many independent matrices at once; returns (results, run_ms).
+    homo_lumo = four sequences (homo_out, homo_in, lumo_in, lumo_out) with one
+    entry per matrix selects SP2-ACC (Alg. 3/4)."""
     own = ctx is None
     if own:
         ctx = BatchContext(Fs[0].device.index or 0)
     try:
         ctx.batch_init(Fs, lambda_min, lambda_max, n_occ, **opts)
+        if homo_lumo is not None:
+            ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
         ctx.batch_run()
         ms, _ = ctx.batch_run_time()
         out = []
@@ -455,14 +481,18 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
               precision: str = "fp64", branch: str = "nearest",
               trunc_tau: float = 0.0, max_iter: int = 100,
               kernel_config: int = 0, tail_split: int = 0,
-              as_fp64: bool = True, ctx: Context | None = None) -> Result:
-    """SP2 (Alg. 2) on the GPU from F to the converged density matrix."""
+              as_fp64: bool = True, ctx: Context | None = None,
+              homo_lumo=None, accelerate: bool = True) -> Result:
+    """SP2 (Alg. 2) on the GPU from F to the converged density matrix; with
+    homo_lumo = (homo_out, homo_in, lumo_in, lumo_out), SP2-ACC (Alg. 3/4)."""
     own = ctx is None
     if own:
         ctx = Context(F.device.index or 0)
     try:
         ctx.init_dense(F, lambda_min, lambda_max, n_occ, precision, branch,
                        trunc_tau, max_iter, kernel_config, tail_split)
+        if homo_lumo is not None:
+            ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
         st = ctx.run()
         D = ctx.get_density(as_fp64=as_fp64)
         n, sq, ms = ctx.get_info()
@@ -475,6 +505,27 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
 
 def status_string(st: int) -> str:
     return load_library().sp2_status_string(st).decode()
+
+
+def acc_schedule(lambda_min, lambda_max, homo_out, homo_in, lumo_in, lumo_out,
+                 accelerate: bool = True):
+    """The library's Alg. 3 schedule (host computation, no device): dict with
+    n_min, n_max and the lists p, alpha of steps 1..n_max."""
+    lib = load_library()
+    cap = MAX_ITER_LIMIT
+    p = (ctypes.c_int8 * cap)()
+    a = (ctypes.c_double * cap)()
+    lo, hi = ctypes.c_int32(), ctypes.c_int32()
+    st = lib.sp2_acc_schedule(float(lambda_min), float(lambda_max), float(homo_out),
+                              float(homo_in), float(lumo_in), float(lumo_out),
+                              1 if accelerate else 0, cap, ctypes.byref(lo),
+                              ctypes.byref(hi), ctypes.cast(p, ctypes.c_void_p),
+                              ctypes.cast(a, ctypes.c_void_p))
+    if st != OK:
+        raise SP2Error(st, "sp2_acc_schedule: bounds not finite, out of order or "
+                           "overlapping")
+    n = hi.value
+    return dict(n_min=lo.value, n_max=n, p=list(p[:n]), alpha=list(a[:n]))
 
 
 def kernel_configs():

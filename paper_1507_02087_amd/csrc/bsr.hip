@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
   }
 }
 
-// (2a) Row bitmaps of Q = P' P' + P' and their popcounts.
+// (2a) Row bitmaps of Q = P' P' + P' + diag and their popcounts.
 __global__ __launch_bounds__(256) void bsr_symbolic_count_kernel(
     BsrIndex idx, int nb, int nbw, uint32_t* bitmap, int32_t* qcnt,
     const DevState* st) {
@@ -94,6 +94,9 @@ __global__ __launch_bounds__(256) void bsr_symbolic_count_kernel(
   for (int w = threadIdx.x; w < nbw; w += 256) bm[w] = 0;
   __syncthreads();
   const int b0 = idx.ptr[I], b1 = idx.ptr[I + 1];
+  // the diagonal block is always kept: the identity term of a stretched
+  // step (Alg. 4) writes it even where the iterate's block is empty
+  if (threadIdx.x == 0) atomicOr(&bm[I >> 5], 1u << (I & 31));
   for (int a = b0; a < b1; ++a) {
     const int K = idx.col[a];
     if (threadIdx.x == 0) atomicOr(&bm[K >> 5], 1u << (K & 31));
@@ -195,7 +198,9 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     }
     return;
   }
-  const int p = st->p[iter];
+  const StepCoef k = step_coef(st->p[iter], st->alpha[iter]);
+  const float ka = static_cast<float>(k.ca), kb = static_cast<float>(k.cb),
+              kc = static_cast<float>(k.cc);
   const double tau = in.tau;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
@@ -262,7 +267,9 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       const double d = static_cast<double>(xo) - static_cast<double>(s);
       const double w = (I == J && m == c) ? 1.0 : 2.0;
       sv += w * d * d;
-      float xn = p ? s : 2.f * xo - s;
+      // X_i = ca S + cb X~ + cc I (identity only inside the matrix proper)
+      float xn = __builtin_fmaf(kb, xo, ka * s);
+      if (I == J && m == c && I * BS + m < n) xn += kc;
       double xd = static_cast<double>(xn);
       if (fabs(xd) < tau) {
         xn = 0.f;
@@ -295,7 +302,6 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     part[3 * blockIdx.x + 1] = sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1];
     part[3 * blockIdx.x + 2] = sh[0][2] + sh[1][2] + sh[2][2] + sh[3][2];
   }
-  (void)n;
 }
 
 // Affine start on the input pattern: X_0 = (lambda_max I - F)/width in FP64,

@@ -59,6 +59,7 @@ __global__ __launch_bounds__(kThreads) void state_reset_kernel(DevState* st,
   __syncthreads();
   if (threadIdx.x == 0) {
     me->p[0] = -1;
+    me->alpha[0] = 1.0;
     if (blockIdx.x == 0) *ndone = 0;
   }
 }
@@ -134,12 +135,14 @@ __device__ __forceinline__ void publish(DevState* st, int32_t* ndone,
 }
 
 // One block per instance: sums the instance's partial triples of step
-// `iter` in a fixed order and applies the scalar part of Alg. 2 on one
-// thread:
+// `iter` in a fixed order and applies the scalar part of Alg. 2 (Alg. 4
+// with a schedule) on one thread:
 //   iter == 0: Tr X~_0, Tr X~_0^2; divergence check; choose p_1 (an
 //     instance with n_occ = 0 or n stops here with n = 0).
 //   iter >= 1: v_{iter-1} from the square of X~_{iter-1}; Tr/Tr^2 of X~_iter;
-//     stop test at k = iter - 1; divergence; max_iter; choose p_{iter+1}.
+//     stop test at k = iter - 1 (from k = 2, or from n_min with a schedule;
+//     a schedule also ends at k = n_max); divergence; max_iter; choose
+//     p_{iter+1} and its stretch.
 __global__ __launch_bounds__(kThreads) void finalize_kernel(
     const Instance* __restrict__ insts, int count,
     const double* __restrict__ part, const double* __restrict__ part_f0,
@@ -160,6 +163,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   if (threadIdx.x != 0) return;
 
   const StopParams& prm = in.prm;
+  const bool sched = prm.n_max > 0;
   const double t1 = b, t2 = c;
   st->t1[iter] = t1;
   st->t2[iter] = t2;
@@ -192,8 +196,13 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
       publish(st, ndone, count, mirror, 0, k);
       return;
     }
-    if (k >= 2 && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
-      publish(st, ndone, count, mirror, 0, k);   // Alg. 2 stop
+    const int kmin = sched ? prm.n_min : 2;
+    if (k >= kmin && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
+      publish(st, ndone, count, mirror, 0, k);   // Alg. 2 / Alg. 4 stop
+      return;
+    }
+    if (sched && k >= prm.n_max) {               // the schedule has ended
+      publish(st, ndone, count, mirror, 0, k);
       return;
     }
     if (!isfinite(t1) || !isfinite(t2) || t2 > t1 + prm.n) {
@@ -205,14 +214,26 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
       return;
     }
   }
-  // Polynomial of the next step from the traces of X~_iter (Alg. 2 branch).
+  // Polynomial of the next step: from the schedule (Alg. 4), or from the
+  // traces of X~_iter (Alg. 2 branch). Past the schedule's end one more
+  // square is needed for v_{n_max}; the iterate it yields is not used.
   int pn;
-  if (prm.branch == 1) {
+  double an = 1.0;
+  if (sched) {
+    const int i = iter + 1;
+    if (i <= prm.n_max) {
+      pn = in.sched_p[i];
+      an = in.sched_alpha[i];
+    } else {
+      pn = 1 - st->p[iter];
+    }
+  } else if (prm.branch == 1) {
     pn = (t1 > prm.n_occ) ? 1 : 0;
   } else {
     pn = (fabs(t2 - prm.n_occ) < fabs(2.0 * t1 - t2 - prm.n_occ)) ? 1 : 0;
   }
   st->p[iter + 1] = static_cast<int8_t>(pn);
+  st->alpha[iter + 1] = an;
 }
 
 template <typename Tin, typename Tout>

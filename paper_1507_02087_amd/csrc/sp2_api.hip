@@ -95,6 +95,9 @@ struct sp2_ctx_s {
   size_t split_cap[4] = {0, 0, 0, 0};
   Instance* d_inst = nullptr;
   size_t d_inst_cap = 0;
+  std::vector<Instance> h_inst;    // host copy of the instance table
+  void* d_sched = nullptr;         // SP2-ACC schedules: alphas, then p's
+  size_t d_sched_cap = 0;
   DevState* d_st = nullptr;
   size_t d_st_cap = 0;
   int2* d_tiles = nullptr;
@@ -437,6 +440,7 @@ sp2_status setup(sp2_ctx c) {
   SP2_HIP(c, grow(c->d_f0, c->d_f0_cap, f0.size() * sizeof(sp2::F0Item), s));
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, inst.data(), count * sizeof(Instance),
                             hipMemcpyHostToDevice, s));
+  c->h_inst = inst;
   if (!tiles.empty())
     SP2_HIP(c, hipMemcpyAsync(c->d_tiles, tiles.data(),
                               tiles.size() * sizeof(int2),
@@ -730,6 +734,7 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->pool[1]);
   for (void* p : c->split_pool) rel(p);
   rel(c->d_inst);
+  rel(c->d_sched);
   rel(c->d_st);
   rel(c->d_tiles);
   rel(c->d_part);
@@ -954,6 +959,7 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, &in, sizeof(Instance),
                             hipMemcpyHostToDevice, s));
   SP2_HIP(c, hipStreamSynchronize(s));
+  c->h_inst.assign(1, in);
   release_groups(c);
   HostInst h;
   h.F = nullptr;
@@ -1085,6 +1091,64 @@ sp2_status sp2_get_info(sp2_ctx c, int32_t* n_iter, int32_t* n_squares,
   if (n_iter) *n_iter = h.n;
   if (n_squares) *n_squares = c->hi[0].trivial ? 0 : h.squares;
   if (run_ms) *run_ms = c->run_ms;
+  return SP2_OK;
+}
+
+sp2_status sp2_set_homo_lumo(sp2_ctx c, int32_t count, const double* homo_out,
+                             const double* homo_in, const double* lumo_in,
+                             const double* lumo_out, int32_t accelerate) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->inited)
+    return fail(c, SP2_BAD_STATE, "no instances: call an init first",
+                hipSuccess);
+  if (count != static_cast<int32_t>(c->hi.size()) ||
+      count != static_cast<int32_t>(c->h_inst.size()))
+    return fail(c, SP2_INVALID_ARG,
+                "count must equal the number of instances of the last init",
+                hipSuccess);
+  if (!homo_out || !homo_in || !lumo_in || !lumo_out)
+    return fail(c, SP2_INVALID_ARG, "NULL bound array", hipSuccess);
+  SP2_HIP(c, hipSetDevice(c->device));
+  const int L = sp2::kMaxIter + 2;   // entries 1..n_max are used
+  std::vector<double> alpha(static_cast<size_t>(count) * L, 1.0);
+  std::vector<int8_t> pol(static_cast<size_t>(count) * L, 0);
+  std::vector<int> nmin(count, 0), nmax(count, 0);
+  for (int b = 0; b < count; ++b) {
+    const HostInst& h = c->hi[b];
+    if (h.trivial) continue;   // stops before any square; no homo/lumo
+    const size_t o = static_cast<size_t>(b) * L + 1;
+    const int rc = sp2::acc_schedule(h.lmin, h.lmax, homo_out[b], homo_in[b],
+                                     lumo_in[b], lumo_out[b], accelerate != 0,
+                                     sp2::kMaxIter, &nmin[b], &nmax[b],
+                                     pol.data() + o, alpha.data() + o);
+    if (rc != 0) {
+      c->err = "instance " + std::to_string(b) +
+               (rc == -1 ? ": homo/lumo bounds not finite, out of order or "
+                           "overlapping"
+                         : ": schedule longer than SP2_MAX_ITER_LIMIT steps");
+      return SP2_INVALID_ARG;
+    }
+  }
+  hipStream_t s = c->stream;
+  const size_t abytes = alpha.size() * sizeof(double);
+  SP2_HIP(c, grow(c->d_sched, c->d_sched_cap, abytes + pol.size(), s));
+  double* d_alpha = static_cast<double*>(c->d_sched);
+  int8_t* d_pol = reinterpret_cast<int8_t*>(static_cast<char*>(c->d_sched) + abytes);
+  SP2_HIP(c, hipMemcpyAsync(d_alpha, alpha.data(), abytes,
+                            hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipMemcpyAsync(d_pol, pol.data(), pol.size(),
+                            hipMemcpyHostToDevice, s));
+  for (int b = 0; b < count; ++b) {
+    Instance& in = c->h_inst[b];
+    in.prm.n_min = nmin[b];
+    in.prm.n_max = nmax[b];
+    in.sched_alpha = nmax[b] ? d_alpha + static_cast<size_t>(b) * L : nullptr;
+    in.sched_p = nmax[b] ? d_pol + static_cast<size_t>(b) * L : nullptr;
+  }
+  SP2_HIP(c, hipMemcpyAsync(c->d_inst, c->h_inst.data(),
+                            count * sizeof(Instance), hipMemcpyHostToDevice, s));
+  // the copies read host vectors that go out of scope
+  SP2_HIP(c, hipStreamSynchronize(s));
   return SP2_OK;
 }
 

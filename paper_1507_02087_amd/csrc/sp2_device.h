@@ -36,7 +36,8 @@ constexpr int kF0Rows = 8;
 // Per-instance state kept in device memory. The finalize kernel is its only
 // writer during a run; the square kernels read `done` and the polynomial of
 // their step from it. Index conventions follow Alg. 2: p[i] is the
-// polynomial that produced X~_i (p[0] unused), v[k] = ||X~_k - X~_k^2||_F,
+// polynomial that produced X~_i (p[0] unused), alpha[i] its stretch (1 in
+// Alg. 2, Alg. 4's alpha_i with a schedule), v[k] = ||X~_k - X~_k^2||_F,
 // t1[k] = Tr X~_k, t2[k] = Tr X~_k^2, r[k] the observed order at step k.
 struct DevState {
   int32_t done;      // 0 while running, 1 once the outcome is fixed
@@ -44,6 +45,7 @@ struct DevState {
   int32_t n;         // index of the returned iterate X~_n
   int32_t squares;   // squares whose partial sums were finalised
   int8_t p[kMaxIter + 2];
+  double alpha[kMaxIter + 2];
   double v[kMaxIter + 1];
   double t1[kMaxIter + 2];
   double t2[kMaxIter + 2];
@@ -58,13 +60,29 @@ struct HostMirror {
   int32_t pad[3];
 };
 
-// Parameters of the scalar stop/branch logic (Alg. 2).
+// Parameters of the scalar stop/branch logic (Alg. 2; Alg. 4 when a
+// schedule is set).
 struct StopParams {
   double n_occ;      // number of occupied states
   double n;          // matrix dimension (divergence test Tr X^2 > Tr X + n)
   int32_t branch;    // 0 = trace-nearest, 1 = literal Tr X > n_occ
   int32_t max_iter;  // squares allowed
+  int32_t n_min;     // schedule: first step where the stop is tested
+  int32_t n_max;     // schedule length; 0 = no schedule (Alg. 2 branch)
 };
+
+// Step i's polynomial written in the square S = X~_{i-1}^2 that the step
+// computes: X_i = ca S + cb X~_{i-1} + cc I. Alg. 4: p = 1 expands
+// ((1 - a) I + a X~)^2 to (a^2, 2a(1 - a), (1 - a)^2), p = 0 expands
+// 2a X~ - (a X~)^2 to (-a^2, 2a, 0). With a = 1 these are exactly Alg. 2's
+// S and 2X~ - S.
+struct StepCoef {
+  double ca, cb, cc;
+};
+__host__ __device__ __forceinline__ StepCoef step_coef(int p, double a) {
+  if (p) return StepCoef{a * a, 2.0 * a * (1.0 - a), (1.0 - a) * (1.0 - a)};
+  return StepCoef{-(a * a), 2.0 * a, 0.0};
+}
 
 // One instance as the kernels see it.
 struct Instance {
@@ -84,6 +102,9 @@ struct Instance {
   double lmax, width;  // lambda_max, lambda_max - lambda_min
   double tau;          // truncation threshold (0 = off)
   StopParams prm;
+  // schedule of Alg. 3, entries 1..prm.n_max (null without a schedule)
+  const int8_t* sched_p;
+  const double* sched_alpha;
 };
 
 // One unit of work of a square launch, given per workgroup by the host:
@@ -112,6 +133,14 @@ struct F0Item {
   int32_t inst;
   int32_t row0;
 };
+
+// Alg. 3 on the host: fills p[i-1], alpha[i-1] for steps i = 1..n_max
+// (arrays of at least `cap` entries, or null) and returns 0, or -1 for
+// bounds out of order / overlapping, -2 for a schedule longer than `cap` or
+// kMaxIter steps.
+int acc_schedule(double lmin, double lmax, double homo_out, double homo_in,
+                 double lumo_in, double lumo_out, bool accelerate, int cap,
+                 int* n_min, int* n_max, int8_t* p, double* alpha);
 
 // A compiled square-kernel configuration.
 struct KernelConfig {

@@ -73,14 +73,33 @@ __device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
   }
 }
 
-// The per-element part of the epilogue. w is the multiplicity of the element
-// in the full symmetric matrix (2 off the diagonal, 1 on it).
+// Step polynomial in the storage type: X_i = ca S + cb X~ + cc I.
 template <typename T>
-__device__ __forceinline__ T epilogue_elem(T s, T xo, int p, double tau,
-                                           double w, bool on_diag, Sums& acc) {
+struct Coef {
+  T ca, cb, cc;
+};
+
+__device__ __forceinline__ double fused(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__device__ __forceinline__ float fused(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+// The per-element part of the epilogue. w is the multiplicity of the element
+// in the full symmetric matrix (2 off the diagonal, 1 on it); on_diag marks
+// a diagonal element of the matrix proper (not of its zero padding, which
+// must stay zero under the identity term). With the
+// coefficients of Alg. 2 (1, 0, 0) and (-1, 2, 0) the new value is exactly S
+// and the single rounding of 2 X~ - S.
+template <typename T>
+__device__ __forceinline__ T epilogue_elem(T s, T xo, const Coef<T>& k,
+                                           double tau, double w, bool on_diag,
+                                           Sums& acc) {
   const double d = static_cast<double>(xo) - static_cast<double>(s);
   acc.v += w * (d * d);
-  T xn = p ? s : T(2) * xo - s;
+  T xn = fused(k.cb, xo, k.ca * s);
+  if (on_diag) xn += k.cc;
   double xd = static_cast<double>(xn);
   if (fabs(xd) < tau) {
     xn = T(0);
@@ -94,20 +113,20 @@ __device__ __forceinline__ T epilogue_elem(T s, T xo, int p, double tau,
 // Applies the epilogue to one accumulator value at tile-local (lr, lc).
 template <typename T>
 __device__ __forceinline__ void epilogue_at(const T* __restrict__ X,
-                                            T* __restrict__ Y, int ld, int I,
-                                            int J, int BM, int lr, int lc,
-                                            T s, int p, double tau,
-                                            Sums& sums) {
+                                            T* __restrict__ Y, int ld, int n,
+                                            int I, int J, int BM, int lr,
+                                            int lc, T s, const Coef<T>& k,
+                                            double tau, Sums& sums) {
   const int gr = I * BM + lr, gc = J * BM + lc;
   const size_t idx = static_cast<size_t>(gr) * ld + gc;
   if (I != J) {
-    const T xn = epilogue_elem<T>(s, *gro(X + idx), p, tau, 2.0, false, sums);
+    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, 2.0, false, sums);
     *grw(Y + idx) = xn;
     *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
   } else if (gr <= gc) {
     const bool on = (gr == gc);
-    const T xn = epilogue_elem<T>(s, *gro(X + idx), p, tau, on ? 1.0 : 2.0, on,
-                                  sums);
+    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, on ? 1.0 : 2.0,
+                                  on && gr < n, sums);
     *grw(Y + idx) = xn;
     if (!on) *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
   }
@@ -151,8 +170,9 @@ struct StepCtx {
   __bf16* Yh;         // BF16x3 split of X~_i (null if absent)
   __bf16* Yl;
   int ld;
+  int n;          // matrix dimension (rows and columns >= n are padding)
   int2 tile;      // (I, J)
-  int p;          // polynomial of step i
+  Coef<T> k;      // polynomial of step i (Alg. 2 / Alg. 4)
   double tau;
 };
 
@@ -167,8 +187,11 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
   c.Yh = static_cast<__bf16*>(in.XH[a.iter & 1]);
   c.Yl = static_cast<__bf16*>(in.XL[a.iter & 1]);
   c.ld = in.ld;
+  c.n = in.n;
   c.tile = a.tiles[slot];
-  c.p = in.st->p[a.iter];
+  const StepCoef sc = step_coef(in.st->p[a.iter], in.st->alpha[a.iter]);
+  c.k = Coef<T>{static_cast<T>(sc.ca), static_cast<T>(sc.cb),
+                static_cast<T>(sc.cc)};
   c.tau = in.tau;
   return c;
 }
@@ -271,7 +294,6 @@ __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
                                              const typename C::Acc& acc) {
   using T = double;
   const int2 tt = sc.tile;
-  const int p = sc.p;
   const T* X = sc.X;
   T* Y = sc.Y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -283,9 +305,9 @@ __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        epilogue_at<T>(X, Y, sc.ld, tt.x, tt.y, C::BM,
+        epilogue_at<T>(X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
                        wm + m * 16 + (lane >> 4) + 4 * j,
-                       wn + n * 16 + (lane & 15), acc.c[m][n][j], p, sc.tau,
+                       wn + n * 16 + (lane & 15), acc.c[m][n][j], sc.k, sc.tau,
                        sums);
   store_partials<C::THREADS>(sums, part, slot);
 }
@@ -371,7 +393,6 @@ __device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
                                              const typename C::Acc& acc) {
   using T = float;
   const int2 tt = sc.tile;
-  const int p = sc.p;
   const T* X = sc.X;
   T* Y = sc.Y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -383,9 +404,9 @@ __device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        epilogue_at<T>(X, Y, sc.ld, tt.x, tt.y, C::BM,
+        epilogue_at<T>(X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
                        wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3),
-                       wn + n * 32 + (lane & 31), acc.c[m][n][j], p, sc.tau,
+                       wn + n * 32 + (lane & 31), acc.c[m][n][j], sc.k, sc.tau,
                        sums);
   store_partials<C::THREADS>(sums, part, slot);
 }
@@ -773,8 +794,9 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       if (diag && gr > gc) continue;
       const size_t idx = static_cast<size_t>(gr) * ld + gc;
       const bool on = (gr == gc);
-      const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx), sc.p,
-                                    sc.tau, on ? 1.0 : 2.0, on, sums);
+      const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx), sc.k,
+                                    sc.tau, on ? 1.0 : 2.0, on && gr < sc.n,
+                                    sums);
       *grw(sc.Y + idx) = xn;
       if (split) store_split(sc.Yh, sc.Yl, idx, xn);
       S[rr * LD + cc] = xn;
