@@ -109,10 +109,18 @@ def test_acc_full_run(prec):
         assert res.r[res.n] < 1.8
     if prec == "fp64":
         assert abs(res.n - ref.n) <= 2
+    # History against the oracle while the error is well above rounding. The
+    # GPU forms a stretched x^2 step as a^2 S + 2a(1 - a) X~ + (1 - a)^2 I
+    # from S = X~^2, so the square's rounding enters scaled by a^2 where the
+    # oracle squares (1 - a) I + a X~ (norm <= 1): allow 100 (k + 1) u_eff
+    # times the product of a_j^2 up to step k.
     u_eff = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
+    amp = 1.0
     for k, (x, y) in enumerate(zip(res.v, ref.v)):
+        if k:
+            amp *= sched.alpha[k] ** 2 if k <= sched.n_max else 1.0
         if y > 1e-3:
-            assert abs(x - y) <= 100 * (k + 1) * u_eff * y + 1e-13, (k, x, y)
+            assert abs(x - y) <= 100 * (k + 1) * u_eff * amp * y + 1e-13, (k, x, y)
     plain = sp2.run_dense(res.D.new_tensor(inst.F), inst.lambda_min, inst.lambda_max,
                           inst.n_occ, precision=prec)
     assert res.n_squares < plain.n_squares
