@@ -24,6 +24,7 @@ from .sp2 import (  # noqa: F401
     g_ratio,
     p_sp1,
     p_sp2,
+    mixed_norm,
 )
 from .sp2acc import (  # noqa: F401
     EPS_M,

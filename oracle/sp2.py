@@ -190,12 +190,36 @@ def _spectral_error(X: np.ndarray, S: np.ndarray) -> float:
     return float(np.max(np.abs(np.linalg.eigvalsh(X - S))))
 
 
+def mixed_norm(A: np.ndarray, block: int) -> float:
+    """Mixed norm (sec. 2, after eq. eq:estim_order_using_frob_norm): A is
+    cut into square blocks of edge ``block`` (zero padding at the end), and
+    the result is the spectral norm of the matrix of the blocks' Frobenius
+    norms. It lies between the spectral and the Frobenius norm of A."""
+    n = A.shape[0]
+    nb = -(-n // block)
+    P = np.zeros((nb * block, nb * block))
+    P[:n, :n] = A
+    M = np.sqrt(np.einsum("ibjc->ij", (P * P).reshape(nb, block, nb, block)))
+    return float(np.linalg.norm(M, 2))
+
+
+def _error(X: np.ndarray, S: np.ndarray, norm: str, mixed_block: int) -> float:
+    """||X - S|| in the requested norm (R1; 'mixed' for large N, sec. 2)."""
+    if norm == "fro":
+        return float(np.linalg.norm(X - S, "fro"))         # eq. eq:frobnorm
+    if norm == "spectral":
+        return _spectral_error(X, S)                        # Alg. 2, e_k
+    if norm == "mixed":
+        return mixed_norm(X - S, mixed_block)
+    raise ValueError(f"unknown norm {norm!r}")
+
+
 # ---------------------------------------------------------------- algorithm
 def sp2(F: np.ndarray, lambda_min: float, lambda_max: float, n_occ: int,
         norm: str = "fro", branch: str = "nearest", tau: float = 0.0,
         max_iter: int = 100,
         perturb: Optional[Callable[[int, np.ndarray], np.ndarray]] = None,
-        working: str = "fp64") -> SP2Result:
+        working: str = "fp64", mixed_block: int = 32) -> SP2Result:
     """Alg. 2 (original SP2 with the new stopping criterion), FP64.
 
     F: symmetric (N, N); lambda_min <= lambda_1 and lambda_max >= lambda_N
@@ -204,7 +228,9 @@ def sp2(F: np.ndarray, lambda_min: float, lambda_max: float, n_occ: int,
     paper's experiments of sec. 4.1 and sec. 5 perturb every iterate).
     ``working`` selects the precision of the matrix square and of the stored
     iterate ("fp64", "fp32", "bf16x3"); traces, errors and the stop test
-    stay in float64 in every mode.
+    stay in float64 in every mode. ``norm`` = "fro", "spectral" or "mixed"
+    (block edge ``mixed_block``); the stop formula is the same for each,
+    with the error two steps back required in (0, 1) (R2).
 
     Loop structure, per step i >= 1: the square S = X~_{i-1}^2 is computed
     once and serves both v_{i-1} = ||X~_{i-1} - S|| (the error that the stop
@@ -217,8 +243,8 @@ def sp2(F: np.ndarray, lambda_min: float, lambda_max: float, n_occ: int,
     if not (0 <= n_occ <= N) or not (lambda_max > lambda_min) \
             or not math.isfinite(lambda_max - lambda_min) or max_iter < 1:
         return SP2Result(None, 0, Status.INVALID_ARG)
-    if norm not in ("fro", "spectral"):
-        raise ValueError(f"unknown norm {norm!r}")
+    if norm not in ("fro", "spectral", "mixed") or mixed_block < 1:
+        raise ValueError(f"unknown norm {norm!r} / block {mixed_block}")
     if n_occ == 0:                                     # R7
         return SP2Result(np.zeros((N, N)), 0, Status.OK)
     if n_occ == N:
@@ -242,10 +268,7 @@ def sp2(F: np.ndarray, lambda_min: float, lambda_max: float, n_occ: int,
         S = _square(X, working)
         S = 0.5 * (S + S.T)                            # R9
         k = i - 1
-        if norm == "fro":
-            vk = float(np.linalg.norm(X - S, "fro"))   # eq. eq:frobnorm
-        else:
-            vk = _spectral_error(X, S)                 # Alg. 2, e_k
+        vk = _error(X, S, norm, mixed_block)
         res.v.append(vk)
         res.r.append(observed_order(vk, res.v[k - 2]) if k >= 2 else float("nan"))
         if not math.isfinite(vk):

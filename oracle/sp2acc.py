@@ -36,7 +36,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from .sp2 import (C_SP2, Q_TILDE, SP2Result, Status, _spectral_error, _square,
+from .sp2 import (C_SP2, Q_TILDE, SP2Result, Status, _error, _square,
                   _store, f0, observed_order, truncate)
 
 EPS_M = float(np.finfo(np.float64).eps)   # R18
@@ -151,7 +151,7 @@ def sp2_acc(F: np.ndarray, lambda_min: float, lambda_max: float,
             sched: Schedule, norm: str = "fro", tau: float = 0.0,
             max_iter: int = 100,
             perturb: Optional[Callable[[int, np.ndarray], np.ndarray]] = None,
-            working: str = "fp64") -> SP2Result:
+            working: str = "fp64", mixed_block: int = 32) -> SP2Result:
     """Alg. 4 with the schedule of Alg. 3.
 
     Per step i = 1..n_max: X_i = ((1 - a_i) I + a_i X~_{i-1})^2 (p_i = 1) or
@@ -173,17 +173,15 @@ def sp2_acc(F: np.ndarray, lambda_min: float, lambda_max: float,
         return SP2Result(None, 0, Status.INVALID_ARG)
     if working not in ("fp64", "fp32"):
         raise ValueError(f"unknown working precision {working!r}")
-    if norm not in ("fro", "spectral"):
-        raise ValueError(f"unknown norm {norm!r}")
+    if norm not in ("fro", "spectral", "mixed") or mixed_block < 1:
+        raise ValueError(f"unknown norm {norm!r} / block {mixed_block}")
     N = F.shape[0]
     eye = np.eye(N)
 
     def error(X):
         S = _square(X, working)
         S = 0.5 * (S + S.T)                           # R9
-        if norm == "fro":
-            return float(np.linalg.norm(X - S, "fro"))
-        return _spectral_error(X, S)
+        return _error(X, S, norm, mixed_block)
 
     X = _store(truncate(f0(F, lambda_min, lambda_max), tau), working)
     if perturb is not None:
