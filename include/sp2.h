@@ -80,6 +80,21 @@ typedef enum {
   SP2_BRANCH_LITERAL = 1   /* Alg. 2 as printed: x^2 iff Tr X > n_occ */
 } sp2_branch;
 
+/* Norm of X~_k - X~_k^2 that the stop test uses (sec. 2). */
+typedef enum {
+  SP2_NORM_FROBENIUS = 0,  /* v_k = ||.||_F (default) */
+  SP2_NORM_MIXED = 1       /* m_k = spectral norm of the matrix of Frobenius
+                              norms of the 32 x 32 blocks (the block size of
+                              sec. 6); spectral <= mixed <= Frobenius, and for
+                              large n it stays below 1 where the Frobenius
+                              norm does not. Evaluated by power iteration on
+                              the block-norm matrix (Rayleigh quotient, FP64,
+                              at most 64 iterations, relative change 1e-7) */
+} sp2_norm;
+
+/* Block edge of SP2_NORM_MIXED. */
+#define SP2_MIXED_BLOCK 32
+
 typedef struct {
   int32_t precision;  /* sp2_precision */
   int32_t branch;     /* sp2_branch */
@@ -99,11 +114,13 @@ typedef struct {
                             of HIP timing events (read back through
                             sp2_get_kernel_times); adds a few microseconds
                             per step */
+  int32_t norm;       /* sp2_norm: the error of the stop test */
+  int32_t reserved;   /* must be 0 */
 } sp2_options;
 
 /* Fills *opt with the defaults: SP2_FP64, SP2_BRANCH_NEAREST, no truncation,
  * max_iter 100, automatic kernel configuration and tail split, no kernel
- * timing. */
+ * timing, Frobenius norm. */
 void sp2_default_options(sp2_options* opt);
 
 /* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -153,6 +170,14 @@ sp2_status sp2_get_density(sp2_ctx ctx, void* D_dev, int64_t ldd,
  * Any pointer may be NULL. Errors: SP2_BAD_STATE before a run. */
 sp2_status sp2_get_info(sp2_ctx ctx, int32_t* n_iter, int32_t* n_squares,
                         double* run_ms);
+
+/* Mixed-norm history of instance `index` of the last run (index 0 for a
+ * dense or block-sparse context): m[k] = ||X~_k - X~_k^2||_M for
+ * k = 0..n_squares-1, with the same conventions as v of sp2_get_history.
+ * Errors: SP2_BAD_STATE before a run or when the run did not use
+ * SP2_NORM_MIXED, SP2_INVALID_ARG. */
+sp2_status sp2_get_mixed_history(sp2_ctx ctx, int32_t index, int32_t cap,
+                                 int32_t* len, double* m);
 
 /* Per-step history of the last run, host arrays of capacity `cap`:
  * v[k] = ||X~_k - X~_k^2||_F for k = 0..n_squares-1; t1[k] = Tr X~_k and

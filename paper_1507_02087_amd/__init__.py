@@ -23,6 +23,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP_ERROR",
                 4: "NOT_CONVERGED", 5: "DIVERGED", 6: "BAD_STATE"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 BRANCHES = {"nearest": 0, "literal": 1}
+NORMS = {"fro": 0, "mixed": 1}
+MIXED_BLOCK = 32
 MAX_ITER_LIMIT = 200
 
 # Exported entry points and their ctypes signatures (mirrors include/sp2.h).
@@ -42,6 +44,8 @@ SIGNATURES = {
                                    _c.c_void_p, _c.c_void_p]),
     "sp2_get_kernel_times": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
                                         _c.c_void_p]),
+    "sp2_get_mixed_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
+                                         _c.POINTER(_c.c_int32), _c.c_void_p]),
     "sp2_init_bsr": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int64,
                                 _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
                                 _c.c_double, _c.c_int64, _c.c_void_p]),
@@ -85,7 +89,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("branch", ctypes.c_int32),
                 ("trunc_tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("kernel_config", ctypes.c_int32), ("tail_split", ctypes.c_int32),
-                ("kernel_timing", ctypes.c_int32)]
+                ("kernel_timing", ctypes.c_int32), ("norm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -135,6 +140,7 @@ class Result:
     t2: list = field(default_factory=list)
     p: list = field(default_factory=list)
     r: list = field(default_factory=list)
+    m: list = field(default_factory=list)    # mixed-norm history (norm="mixed")
 
     @property
     def status_name(self) -> str:
@@ -226,7 +232,7 @@ class Context:
                    precision: str = "fp64", branch: str = "nearest",
                    trunc_tau: float = 0.0, max_iter: int = 100,
                    kernel_config: int = 0, tail_split: int = 0,
-                   kernel_timing: bool = False):
+                   kernel_timing: bool = False, norm: str = "fro"):
         import torch
         if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
             raise TypeError("F must be a float64 CUDA tensor")
@@ -234,7 +240,7 @@ class Context:
             raise ValueError("F must be square with unit column stride")
         opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
                       int(max_iter), int(kernel_config), int(tail_split),
-                      1 if kernel_timing else 0)
+                      1 if kernel_timing else 0, NORMS[norm], 0)
         self._F = F   # keep alive until run() returns
         st = self._lib.sp2_init_dense(self._h, ctypes.c_void_p(F.data_ptr()),
                                       F.shape[0], F.stride(0), float(lambda_min),
@@ -283,6 +289,17 @@ class Context:
                                                 1 if accelerate else 0),
                     "sp2_set_homo_lumo")
 
+    def get_mixed_history(self, index: int = 0):
+        """m[k] = mixed norm of X~_k - X~_k^2 of the last run (norm="mixed")."""
+        import numpy as np
+        ln = ctypes.c_int32()
+        m = np.full(MAX_ITER_LIMIT + 1, np.nan)
+        self._check(self._lib.sp2_get_mixed_history(self._h, index, m.size,
+                                                    ctypes.byref(ln),
+                                                    ctypes.c_void_p(m.ctypes.data)),
+                    "sp2_get_mixed_history")
+        return m[:ln.value].tolist()
+
     def get_config(self, index: int = 0):
         """(id, name) of the square-kernel configuration instance `index`
         uses; (0, None) where no square is computed."""
@@ -326,7 +343,7 @@ class BsrContext(Context):
     def init_bsr(self, n: int, row_ptr, col_idx, blocks, lambda_min: float,
                  lambda_max: float, n_occ: int, trunc_tau: float = 0.0,
                  branch: str = "nearest", max_iter: int = 100,
-                 kernel_timing: bool = False):
+                 kernel_timing: bool = False, norm: str = "fro"):
         """row_ptr/col_idx: int32 CUDA tensors; blocks: float64 CUDA tensor of
         shape (nnzb, 32, 32)."""
         import torch
@@ -337,7 +354,7 @@ class BsrContext(Context):
         if not (row_ptr.is_cuda and col_idx.is_cuda and blocks.is_cuda):
             raise TypeError("arrays must be CUDA tensors")
         opt = Options(PRECISIONS["fp32"], BRANCHES[branch], float(trunc_tau),
-                      int(max_iter), 0, 0, 1 if kernel_timing else 0)
+                      int(max_iter), 0, 0, 1 if kernel_timing else 0, NORMS[norm], 0)
         self._keep = (row_ptr, col_idx, blocks)
         st = self._lib.sp2_init_bsr(self._h, int(n), 32, int(col_idx.numel()),
                                     ctypes.c_void_p(row_ptr.data_ptr()),
@@ -390,7 +407,7 @@ class BatchContext(Context):
     def batch_init(self, Fs, lambda_min, lambda_max, n_occ, precision: str = "fp64",
                    branch: str = "nearest", trunc_tau: float = 0.0,
                    max_iter: int = 100, kernel_config: int = 0, tail_split: int = 0,
-                   kernel_timing: bool = False):
+                   kernel_timing: bool = False, norm: str = "fro"):
         import torch
         for F in Fs:
             if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
@@ -400,7 +417,7 @@ class BatchContext(Context):
         cnt = len(Fs)
         opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
                       int(max_iter), int(kernel_config), int(tail_split),
-                      1 if kernel_timing else 0)
+                      1 if kernel_timing else 0, NORMS[norm], 0)
         self._Fs = list(Fs)   # keep alive until batch_run() returns
         ptrs = _arr(ctypes.c_void_p, [F.data_ptr() for F in Fs])
         ns = _arr(ctypes.c_int64, [F.shape[0] for F in Fs])
@@ -469,7 +486,8 @@ def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None
         out = []
         for b in range(len(Fs)):
             D, st, n, sq = ctx.batch_get(b, as_fp64=as_fp64)
-            out.append(Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms,
+            m = ctx.get_mixed_history(b) if opts.get("norm") == "mixed" else []
+            out.append(Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, m=m,
                               **ctx.batch_history(b)))
         return out, ms
     finally:
@@ -482,7 +500,7 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
               trunc_tau: float = 0.0, max_iter: int = 100,
               kernel_config: int = 0, tail_split: int = 0,
               as_fp64: bool = True, ctx: Context | None = None,
-              homo_lumo=None, accelerate: bool = True) -> Result:
+              homo_lumo=None, accelerate: bool = True, norm: str = "fro") -> Result:
     """SP2 (Alg. 2) on the GPU from F to the converged density matrix; with
     homo_lumo = (homo_out, homo_in, lumo_in, lumo_out), SP2-ACC (Alg. 3/4)."""
     own = ctx is None
@@ -490,14 +508,15 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
         ctx = Context(F.device.index or 0)
     try:
         ctx.init_dense(F, lambda_min, lambda_max, n_occ, precision, branch,
-                       trunc_tau, max_iter, kernel_config, tail_split)
+                       trunc_tau, max_iter, kernel_config, tail_split, norm=norm)
         if homo_lumo is not None:
             ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
         st = ctx.run()
         D = ctx.get_density(as_fp64=as_fp64)
         n, sq, ms = ctx.get_info()
         h = ctx.get_history()
-        return Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, **h)
+        m = ctx.get_mixed_history() if norm == "mixed" else []
+        return Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, m=m, **h)
     finally:
         if own:
             ctx.close()

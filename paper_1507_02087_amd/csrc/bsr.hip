@@ -258,6 +258,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     float* out = B.val + static_cast<size_t>(q) * BE;
     float* outT = B.val + static_cast<size_t>(qT) * BE;
     bool nz = false;
+    double bsq = 0.0;   // squared Frobenius norm of this block of X~ - S
     for (int j = 0; j < 16; ++j) {
       const int m = 8 * (j >> 2) + 4 * h + (j & 3);   // row in the block
       const int c = r;                                // column in the block
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       const double d = static_cast<double>(xo) - static_cast<double>(s);
       const double w = (I == J && m == c) ? 1.0 : 2.0;
       sv += w * d * d;
+      bsq += (I == J) ? w * d * d : d * d;
       // X_i = ca S + cb X~ + cc I (identity only inside the matrix proper)
       float xn = __builtin_fmaf(kb, xo, ka * s);
       if (I == J && m == c && I * BS + m < n) xn += kc;
@@ -285,6 +287,15 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     if (lane == 0) {
       B.flag[q] = any;
       B.flag[qT] = any;
+    }
+    if (in.blk) {
+      // mixed norm: one value per block of the output pattern
+      bsq = wave_sum(bsq);
+      if (lane == 0) {
+        const float bn = static_cast<float>(sqrt(bsq));
+        *grw(in.blk + q) = bn;
+        *grw(in.blk + qT) = bn;
+      }
     }
   }
   sv = wave_sum(sv);

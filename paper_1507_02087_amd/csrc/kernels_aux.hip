@@ -121,6 +121,68 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   }
 }
 
+// Sum over the workgroup, returned to every thread (fixed order).
+__device__ __forceinline__ double block_sum_all(double x, double* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();   // red may still be read from a previous call
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) t += red[w];
+  return t;
+}
+
+constexpr int kPowerIters = 64;       // power-iteration cap
+constexpr double kPowerTol = 1e-7;    // relative change that ends it
+constexpr int kMaxBlockRows = 2048;   // n / 32 for n <= 65536
+
+// Mixed norm of X~_{iter-1} - S (sec. 2): the spectral norm of the
+// symmetric, nonnegative matrix M of block Frobenius norms that the step's
+// epilogues wrote, i.e. its Perron root, by power iteration from the
+// all-ones vector with Rayleigh quotients x.Mx / x.x, in FP64. Every thread
+// of the workgroup takes part and receives the result.
+__device__ double mixed_norm(const Instance& in, int iter, double* x,
+                             double* y, double* red) {
+  const int nb = in.nbk;
+  const bool sparse = (in.brp[0] != nullptr);
+  const int32_t* rp = sparse ? in.brp[iter & 1] : nullptr;
+  const int32_t* col = sparse ? in.bcol[iter & 1] : nullptr;
+  for (int i = threadIdx.x; i < nb; i += kThreads) x[i] = 1.0;
+  double lam = 0.0;
+  for (int it = 0; it < kPowerIters; ++it) {
+    __syncthreads();
+    double xy = 0.0, xx = 0.0, yy = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
+      double acc = 0.0;
+      if (sparse) {
+        for (int q = rp[i]; q < rp[i + 1]; ++q)
+          acc += static_cast<double>(in.blk[q]) * x[col[q]];
+      } else {
+        // M is symmetric: walk column i so that neighbouring threads read
+        // neighbouring addresses
+        for (int j = 0; j < nb; ++j)
+          acc += static_cast<double>(in.blk[static_cast<size_t>(j) * nb + i]) *
+                 x[j];
+      }
+      y[i] = acc;
+      xy += x[i] * acc;
+      xx += x[i] * x[i];
+      yy += acc * acc;
+    }
+    xy = block_sum_all(xy, red);
+    xx = block_sum_all(xx, red);
+    yy = block_sum_all(yy, red);
+    const double prev = lam;
+    lam = (xx > 0.0) ? xy / xx : 0.0;
+    if (!(yy > 0.0) || !isfinite(yy)) break;   // M = 0, or not finite
+    const double s = 1.0 / sqrt(yy);
+    for (int i = threadIdx.x; i < nb; i += kThreads) x[i] = y[i] * s;
+    if (it > 0 && fabs(lam - prev) <= kPowerTol * lam) break;
+  }
+  return lam;
+}
+
 __device__ __forceinline__ void publish(DevState* st, int32_t* ndone,
                                         int count, HostMirror* m, int status,
                                         int n) {
@@ -160,9 +222,14 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     c += pp[3 * i + 2];
   }
   block_sum3(a, b, c, sh);
+  const StopParams& prm = in.prm;
+  double mk = 0.0;
+  if (iter >= 1 && prm.norm == 1) {
+    __shared__ double xs[kMaxBlockRows], ys[kMaxBlockRows], red[kThreads / 64];
+    mk = mixed_norm(in, iter, xs, ys, red);
+  }
   if (threadIdx.x != 0) return;
 
-  const StopParams& prm = in.prm;
   const bool sched = prm.n_max > 0;
   const double t1 = b, t2 = c;
   st->t1[iter] = t1;
@@ -180,12 +247,16 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     const int k = iter - 1;
     const double vk = sqrt(a);
     st->v[k] = vk;
+    st->m[k] = mk;
     st->squares = iter;
+    // the error the stop test reads: Frobenius, or mixed (sec. 2)
+    const double* e = (prm.norm == 1) ? st->m : st->v;
+    const double ek = e[k];
     double r = NAN;
     if (k >= 2) {
-      const double vkm2 = st->v[k - 2];
-      if (vkm2 > 0.0 && vkm2 < 1.0 && vk > 0.0)
-        r = log(vk / c_sp2()) / log(vkm2);   // observed order (sec. 2)
+      const double ekm2 = e[k - 2];
+      if (ekm2 > 0.0 && ekm2 < 1.0 && ek > 0.0)
+        r = log(ek / c_sp2()) / log(ekm2);   // observed order (sec. 2)
     }
     st->r[k] = r;
     if (!isfinite(vk)) {

@@ -98,6 +98,8 @@ struct sp2_ctx_s {
   std::vector<Instance> h_inst;    // host copy of the instance table
   void* d_sched = nullptr;         // SP2-ACC schedules: alphas, then p's
   size_t d_sched_cap = 0;
+  float* d_blk = nullptr;          // block norms of the mixed norm
+  size_t d_blk_cap = 0;
   DevState* d_st = nullptr;
   size_t d_st_cap = 0;
   int2* d_tiles = nullptr;
@@ -286,6 +288,11 @@ sp2_status validate_options(sp2_ctx c, sp2_options& opt) {
   }
   if (opt.tail_split < 0 || opt.tail_split > 64)
     return fail(c, SP2_INVALID_ARG, "tail_split outside [0, 64]", hipSuccess);
+  if (opt.norm != SP2_NORM_FROBENIUS && opt.norm != SP2_NORM_MIXED)
+    return fail(c, SP2_INVALID_ARG, "unknown norm", hipSuccess);
+  if (opt.reserved != 0)
+    return fail(c, SP2_INVALID_ARG, "reserved option field must be 0",
+                hipSuccess);
   return SP2_OK;
 }
 
@@ -344,6 +351,18 @@ sp2_status setup(sp2_ctx c) {
     for (int q = 0; q < 4; ++q)
       SP2_HIP(c, grow(c->split_pool[q], c->split_cap[q], pool_elems * 2, s));
 
+  // block norms of the mixed norm: an (np/32)^2 matrix per instance
+  const bool mixed = (c->opt.norm == SP2_NORM_MIXED);
+  std::vector<size_t> blk_off(count, 0);
+  size_t blk_elems = 0;
+  for (int b = 0; b < count; ++b) {
+    blk_off[b] = blk_elems;
+    const size_t nbk = static_cast<size_t>(c->hi[b].np / sp2::kMixedBlock);
+    if (mixed) blk_elems += (nbk * nbk + 63) / 64 * 64;
+  }
+  if (mixed)
+    SP2_HIP(c, grow(c->d_blk, c->d_blk_cap, blk_elems * sizeof(float), s));
+
   // instance table, tiles and affine-start blocks
   SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
   std::vector<int2> tiles;
@@ -380,6 +399,9 @@ sp2_status setup(sp2_ctx c) {
     in.prm.n = static_cast<double>(h.n);
     in.prm.branch = c->opt.branch;
     in.prm.max_iter = c->opt.max_iter;
+    in.prm.norm = c->opt.norm;
+    in.nbk = static_cast<int>(h.np / sp2::kMixedBlock);
+    in.blk = mixed ? c->d_blk + blk_off[b] : nullptr;
   }
 
   // launch groups: one per configuration in use (trivial instances stop
@@ -635,6 +657,8 @@ void sp2_default_options(sp2_options* opt) {
   opt->kernel_config = 0;
   opt->tail_split = 0;
   opt->kernel_timing = 0;
+  opt->norm = SP2_NORM_FROBENIUS;
+  opt->reserved = 0;
 }
 
 const char* sp2_status_string(sp2_status s) {
@@ -735,6 +759,7 @@ sp2_status sp2_destroy(sp2_ctx c) {
   for (void* p : c->split_pool) rel(p);
   rel(c->d_inst);
   rel(c->d_sched);
+  rel(c->d_blk);
   rel(c->d_st);
   rel(c->d_tiles);
   rel(c->d_part);
@@ -953,6 +978,18 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   in.prm.n = static_cast<double>(n);
   in.prm.branch = opt.branch;
   in.prm.max_iter = opt.max_iter;
+  in.prm.norm = opt.norm;
+  in.nbk = nb;
+  if (opt.norm == SP2_NORM_MIXED) {
+    // one block norm per block of the output pattern
+    SP2_HIP(c, grow(c->d_blk, c->d_blk_cap,
+                    static_cast<size_t>(cap) * sizeof(float), s));
+    in.blk = c->d_blk;
+    for (int k = 0; k < 2; ++k) {
+      in.brp[k] = c->b.m[k].row_ptr;
+      in.bcol[k] = c->b.m[k].col;
+    }
+  }
   SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, sizeof(Instance), s));
   SP2_HIP(c, grow(c->d_part, c->d_part_cap, grid * 3 * sizeof(double), s));
   SP2_HIP(c, grow(c->d_part_f0, c->d_part_f0_cap, nnzb * 3 * sizeof(double), s));
@@ -1091,6 +1128,23 @@ sp2_status sp2_get_info(sp2_ctx c, int32_t* n_iter, int32_t* n_squares,
   if (n_iter) *n_iter = h.n;
   if (n_squares) *n_squares = c->hi[0].trivial ? 0 : h.squares;
   if (run_ms) *run_ms = c->run_ms;
+  return SP2_OK;
+}
+
+sp2_status sp2_get_mixed_history(sp2_ctx c, int32_t index, int32_t cap,
+                                 int32_t* len, double* m) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran || c->opt.norm != SP2_NORM_MIXED)
+    return fail(c, SP2_BAD_STATE, "no completed run with the mixed norm",
+                hipSuccess);
+  if (index < 0 || index >= static_cast<int32_t>(c->host_state.size()) ||
+      cap < 0)
+    return fail(c, SP2_INVALID_ARG, "index or cap out of range", hipSuccess);
+  const DevState& h = c->host_state[index];
+  const int cnt = c->hi[index].trivial ? 0 : h.squares;
+  if (len) *len = cnt;
+  if (m)
+    for (int k = 0; k < cnt && k < cap; ++k) m[k] = h.m[k];
   return SP2_OK;
 }
 

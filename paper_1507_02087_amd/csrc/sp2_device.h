@@ -47,6 +47,7 @@ struct DevState {
   int8_t p[kMaxIter + 2];
   double alpha[kMaxIter + 2];
   double v[kMaxIter + 1];
+  double m[kMaxIter + 1];   // mixed norm ||X~_k - X~_k^2||_M (mixed mode)
   double t1[kMaxIter + 2];
   double t2[kMaxIter + 2];
   double r[kMaxIter + 1];
@@ -69,7 +70,12 @@ struct StopParams {
   int32_t max_iter;  // squares allowed
   int32_t n_min;     // schedule: first step where the stop is tested
   int32_t n_max;     // schedule length; 0 = no schedule (Alg. 2 branch)
+  int32_t norm;      // error fed to the stop: 0 Frobenius, 1 mixed
+  int32_t pad;
 };
+
+// Edge of the blocks of the mixed norm (the block size of sec. 6).
+constexpr int kMixedBlock = 32;
 
 // Step i's polynomial written in the square S = X~_{i-1}^2 that the step
 // computes: X_i = ca S + cb X~_{i-1} + cc I. Alg. 4: p = 1 expands
@@ -105,6 +111,16 @@ struct Instance {
   // schedule of Alg. 3, entries 1..prm.n_max (null without a schedule)
   const int8_t* sched_p;
   const double* sched_alpha;
+  // Mixed norm (null unless prm.norm == 1): Frobenius norms of the 32 x 32
+  // blocks of X~_{i-1} - S, written by the step's epilogues. Dense: an
+  // nbk x nbk row-major matrix (nbk = ld / 32). Block-sparse: one value per
+  // block of the step's output pattern, whose row pointers and columns are
+  // brp/bcol[i & 1] (nbk block rows).
+  float* blk;
+  int nbk;
+  int pad_blk;
+  const int32_t* brp[2];
+  const int32_t* bcol[2];
 };
 
 // One unit of work of a square launch, given per workgroup by the host:

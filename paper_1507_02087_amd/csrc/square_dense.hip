@@ -95,9 +95,10 @@ __device__ __forceinline__ float fused(float a, float b, float c) {
 template <typename T>
 __device__ __forceinline__ T epilogue_elem(T s, T xo, const Coef<T>& k,
                                            double tau, double w, bool on_diag,
-                                           Sums& acc) {
+                                           Sums& acc, double& d2) {
   const double d = static_cast<double>(xo) - static_cast<double>(s);
-  acc.v += w * (d * d);
+  d2 = d * d;
+  acc.v += w * d2;
   T xn = fused(k.cb, xo, k.ca * s);
   if (on_diag) xn += k.cc;
   double xd = static_cast<double>(xn);
@@ -110,26 +111,59 @@ __device__ __forceinline__ T epilogue_elem(T s, T xo, const Coef<T>& k,
   return xn;
 }
 
-// Applies the epilogue to one accumulator value at tile-local (lr, lc).
+// Contribution of one processed element to the squared Frobenius norm of
+// its 32 x 32 block of X~ - S: inside a diagonal block only the upper
+// triangle is processed, so an off-diagonal element there stands for itself
+// and its mirror.
+__device__ __forceinline__ double block_share(int gr, int gc, double d2) {
+  return (gr / kMixedBlock == gc / kMixedBlock && gr != gc) ? 2.0 * d2 : d2;
+}
+
+// Stores the Frobenius norm of block (rb, cb) of X~ - S and of its mirror.
+__device__ __forceinline__ void blk_write(float* blk, int nbk, int rb, int cb,
+                                          double sum) {
+  const float v = static_cast<float>(sqrt(sum));
+  *grw(blk + static_cast<size_t>(rb) * nbk + cb) = v;
+  *grw(blk + static_cast<size_t>(cb) * nbk + rb) = v;
+}
+
+// Applies the epilogue to one accumulator value at tile-local (lr, lc);
+// returns the element's share of its block's squared norm (0 if the element
+// is a mirrored one that this tile does not process).
 template <typename T>
-__device__ __forceinline__ void epilogue_at(const T* __restrict__ X,
-                                            T* __restrict__ Y, int ld, int n,
-                                            int I, int J, int BM, int lr,
-                                            int lc, T s, const Coef<T>& k,
-                                            double tau, Sums& sums) {
+__device__ __forceinline__ double epilogue_at(const T* __restrict__ X,
+                                              T* __restrict__ Y, int ld, int n,
+                                              int I, int J, int BM, int lr,
+                                              int lc, T s, const Coef<T>& k,
+                                              double tau, Sums& sums) {
   const int gr = I * BM + lr, gc = J * BM + lc;
   const size_t idx = static_cast<size_t>(gr) * ld + gc;
+  double d2 = 0.0;
   if (I != J) {
-    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, 2.0, false, sums);
+    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, 2.0, false, sums,
+                                  d2);
     *grw(Y + idx) = xn;
     *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
+    return d2;
   } else if (gr <= gc) {
     const bool on = (gr == gc);
     const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, on ? 1.0 : 2.0,
-                                  on && gr < n, sums);
+                                  on && gr < n, sums, d2);
     *grw(Y + idx) = xn;
     if (!on) *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
+    return block_share(gr, gc, d2);
   }
+  return 0.0;
+}
+
+// Sum over the 32 lanes of a half wave (fixed order).
+__device__ __forceinline__ double half_wave_sum(double x) {
+  for (int off = 16; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ double full_wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
 }
 
 // Global -> register staging of a BM x BK slice of two row panels, in
@@ -174,6 +208,8 @@ struct StepCtx {
   int2 tile;      // (I, J)
   Coef<T> k;      // polynomial of step i (Alg. 2 / Alg. 4)
   double tau;
+  float* blk;     // block norms of X~_{i-1} - S (mixed norm), or null
+  int nbk;
 };
 
 template <typename T>
@@ -193,6 +229,8 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
   c.k = Coef<T>{static_cast<T>(sc.ca), static_cast<T>(sc.cb),
                 static_cast<T>(sc.cc)};
   c.tau = in.tau;
+  c.blk = in.blk;
+  c.nbk = in.nbk;
   return c;
 }
 
@@ -299,16 +337,31 @@ __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   Sums sums;
+  // 16 x 16 fragments: block (m / 2, n / 2) of the wave's region is made of
+  // fragments m, m + 1 and n, n + 1
+  static_assert(C::TM % kMixedBlock == 0 && C::TN % kMixedBlock == 0, "blocks");
+  double bs[C::MB / 2][C::NB / 2] = {};
 #pragma unroll
   for (int m = 0; m < C::MB; ++m)
 #pragma unroll
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        epilogue_at<T>(X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
-                       wm + m * 16 + (lane >> 4) + 4 * j,
-                       wn + n * 16 + (lane & 15), acc.c[m][n][j], sc.k, sc.tau,
-                       sums);
+        bs[m / 2][n / 2] += epilogue_at<T>(
+            X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
+            wm + m * 16 + (lane >> 4) + 4 * j, wn + n * 16 + (lane & 15),
+            acc.c[m][n][j], sc.k, sc.tau, sums);
+  if (sc.blk) {
+#pragma unroll
+    for (int a = 0; a < C::MB / 2; ++a)
+#pragma unroll
+      for (int b = 0; b < C::NB / 2; ++b) {
+        const double t = full_wave_sum(bs[a][b]);
+        const int rb = (tt.x * C::BM + wm) / kMixedBlock + a;
+        const int cb = (tt.y * C::BM + wn) / kMixedBlock + b;
+        if (lane == 0 && rb <= cb) blk_write(sc.blk, sc.nbk, rb, cb, t);
+      }
+  }
   store_partials<C::THREADS>(sums, part, slot);
 }
 
@@ -398,16 +451,25 @@ __device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   Sums sums;
+  // a 32 x 32 fragment is one block of the mixed norm
 #pragma unroll
   for (int m = 0; m < C::MB; ++m)
 #pragma unroll
-    for (int n = 0; n < C::NB; ++n)
+    for (int n = 0; n < C::NB; ++n) {
+      double bs = 0.0;
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        epilogue_at<T>(X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
-                       wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3),
-                       wn + n * 32 + (lane & 31), acc.c[m][n][j], sc.k, sc.tau,
-                       sums);
+        bs += epilogue_at<T>(
+            X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
+            wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3),
+            wn + n * 32 + (lane & 31), acc.c[m][n][j], sc.k, sc.tau, sums);
+      if (sc.blk) {
+        const double t = full_wave_sum(bs);
+        const int rb = (tt.x * C::BM + wm) / kMixedBlock + m;
+        const int cb = (tt.y * C::BM + wn) / kMixedBlock + n;
+        if (lane == 0 && rb <= cb) blk_write(sc.blk, sc.nbk, rb, cb, t);
+      }
+    }
   store_partials<C::THREADS>(sums, part, slot);
 }
 
@@ -763,6 +825,11 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
                                                  char* smem) {
   using T = float;
   constexpr int BM = C::BM, TM = C::TM, LD = BM + 1;
+  constexpr int R = C::THREADS / BM;   // rows of a band one pass covers
+  static_assert(C::THREADS % BM == 0 && kMixedBlock % R == 0 &&
+                    TM % kMixedBlock == 0 && BM % 64 == 0,
+                "epilogue thread layout");
+  __shared__ double bred[R][TM / kMixedBlock][BM / kMixedBlock];
   T* S = reinterpret_cast<T*>(smem);
   const int2 tt = sc.tile;
   const int I = tt.x, J = tt.y;
@@ -788,20 +855,44 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
     }
     __syncthreads();
     const int r0 = I * BM + g * TM;
-    for (int e = tid; e < TM * BM; e += C::THREADS) {
-      const int rr = e / BM, cc = e % BM;
-      const int gr = r0 + rr, gc = J * BM + cc;
-      if (diag && gr > gc) continue;
-      const size_t idx = static_cast<size_t>(gr) * ld + gc;
-      const bool on = (gr == gc);
-      const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx), sc.k,
-                                    sc.tau, on ? 1.0 : 2.0, on && gr < sc.n,
-                                    sums);
-      *grw(sc.Y + idx) = xn;
-      if (split) store_split(sc.Yh, sc.Yl, idx, xn);
-      S[rr * LD + cc] = xn;
+    // Thread tid owns column cc = tid % BM and the rows ph + R j of the band
+    // (ph = tid / BM): the elements e = tid + THREADS j in row-major order.
+    // Rows are visited one 32-row block at a time so that the block sums of
+    // the mixed norm are complete after each block row.
+    const int cc = tid % BM, ph = tid / BM;
+    const int gc = J * BM + cc;
+    for (int rb = 0; rb < TM / kMixedBlock; ++rb) {
+      double bs = 0.0;
+      for (int jj = 0; jj < kMixedBlock / R; ++jj) {
+        const int rr = rb * kMixedBlock + ph + R * jj;
+        const int gr = r0 + rr;
+        if (!(diag && gr > gc)) {
+          const size_t idx = static_cast<size_t>(gr) * ld + gc;
+          const bool on = (gr == gc);
+          double d2;
+          const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx),
+                                        sc.k, sc.tau, on ? 1.0 : 2.0,
+                                        on && gr < sc.n, sums, d2);
+          *grw(sc.Y + idx) = xn;
+          if (split) store_split(sc.Yh, sc.Yl, idx, xn);
+          S[rr * LD + cc] = xn;
+          bs += block_share(gr, gc, d2);
+        }
+      }
+      if (sc.blk) {
+        // the 32 lanes of a half wave hold the 32 columns of one block
+        bs = half_wave_sum(bs);
+        if ((lane & 31) == 0) bred[ph][rb][cc / kMixedBlock] = bs;
+      }
     }
     __syncthreads();
+    if (sc.blk && tid < (TM / kMixedBlock) * (BM / kMixedBlock)) {
+      const int rb = tid / (BM / kMixedBlock), cb = tid % (BM / kMixedBlock);
+      double t = 0.0;
+      for (int q = 0; q < R; ++q) t += bred[q][rb][cb];
+      const int grb = r0 / kMixedBlock + rb, gcb = J * BM / kMixedBlock + cb;
+      if (grb <= gcb) blk_write(sc.blk, sc.nbk, grb, gcb, t);
+    }
     for (int e = tid; e < TM * BM; e += C::THREADS) {
       const int cc = e / TM, rr = e % TM;
       const int gr = r0 + rr, gc = J * BM + cc;
