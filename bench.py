@@ -283,6 +283,8 @@ def main() -> int:
     ap.add_argument("--cpu-squares", type=int, default=5)
     ap.add_argument("--config", type=int, default=0,
                     help="square-kernel configuration id (0 = library choice)")
+    ap.add_argument("--no-acc", action="store_true",
+                    help="skip the SP2-ACC comparison run (dense workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB twice with torch (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -433,6 +435,32 @@ def main() -> int:
         squares_cpu = sq64
     else:
         squares_cpu = n_sq
+
+    if not args.no_acc:
+        # SP2-ACC (Alg. 3/4) on the same input with the construction's exact
+        # homo and lumo eigenvalues as bounds, same precision
+        log("[bench] SP2-ACC comparison run")
+        h = float(inst.lam[inst.n_occ - 1])
+        l = float(inst.lam[inst.n_occ])
+        sched = sp2.acc_schedule(inst.lambda_min, inst.lambda_max, h, h, l, l)
+        acc_ms = []
+        for _ in range(max(1, args.steps)):
+            ctx.init_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,
+                           precision=prec)
+            ctx.set_homo_lumo(h, h, l, l)
+            sta = ctx.run()
+            na, sqa, msa = ctx.get_info()
+            acc_ms.append(msa)
+        Da = ctx.get_density(as_fp64=True).cpu().numpy()
+        Qo = inst.Q[:, :inst.n_occ]
+        erra = float(np.linalg.norm(Da - Qo @ Qo.T))
+        del Da
+        out["acc"] = {
+            "time_to_D_ms": round(float(np.median(acc_ms)), 3), "n_iter": na,
+            "n_squares": sqa, "n_min": sched["n_min"], "n_max": sched["n_max"],
+            "status": sp2.STATUS_NAMES[sta], "err_fro_vs_exact_D": erra,
+            "speedup_vs_sp2": round(out["value"] / float(np.median(acc_ms)), 2),
+        }
 
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample ({args.cpu_squares} squares)")

@@ -57,8 +57,10 @@ def test_first_mixed_norm_every_config(prec, cfg, n, split):
     assert res.status_name == "NOT_CONVERGED" and len(res.m) == 1
     tol = n * square_bound(n, prec) + M_REL * ref.v[0]
     assert abs(res.m[0] - ref.v[0]) <= tol, (res.m[0], ref.v[0], tol)
-    # the Frobenius error is still reported, and m <= v
-    assert res.m[0] <= res.v[0] * (1 + 1e-12)
+    # the Frobenius error is still reported, and m <= v (block norms are
+    # stored in FP32: up to one FP32 rounding above v when one block holds
+    # the whole matrix)
+    assert res.m[0] <= res.v[0] * (1 + 2.0 ** -22)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
