@@ -6,7 +6,7 @@ library or its Python binding. It shares no code with the GPU path: it is a
 plain, slow, step-by-step restatement of the paper's algorithm in NumPy
 float64 (Kruchinina, Rudberg, Rubensson, "Parameterless stopping criteria
 for recursive density matrix expansions", Alg. 2 and sec. 2; SP2-ACC,
-Alg. 3 and Alg. 4).
+Alg. 3 and Alg. 4; McWeeny and McW-ACC, sec. 3).
 """
 from .sp2 import (  # noqa: F401
     C_SP2,
@@ -34,4 +34,13 @@ from .sp2acc import (  # noqa: F401
     acc_schedule,
     acc_polynomial,
     sp2_acc,
+)
+from .mcweeny import (  # noqa: F401
+    C_MW,
+    p_mw,
+    f0_mw,
+    mw_gamma,
+    mwa_alpha,
+    p_mwa,
+    mcweeny,
 )
