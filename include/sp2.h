@@ -87,9 +87,12 @@ typedef enum {
                               norms of the 32 x 32 blocks (the block size of
                               sec. 6); spectral <= mixed <= Frobenius, and for
                               large n it stays below 1 where the Frobenius
-                              norm does not. Evaluated by power iteration on
-                              the block-norm matrix (Rayleigh quotient, FP64,
-                              at most 64 iterations, relative change 1e-7) */
+                              norm does not. The spectral norm of the
+                              block-norm matrix is its largest eigenvalue,
+                              found by Lanczos (FP64, full
+                              reorthogonalisation, at most 64 steps, until
+                              the top Ritz value changes by < 1e-12
+                              relative) */
 } sp2_norm;
 
 /* Block edge of SP2_NORM_MIXED. */

@@ -133,54 +133,133 @@ __device__ __forceinline__ double block_sum_all(double x, double* red) {
   return t;
 }
 
-constexpr int kPowerIters = 64;       // power-iteration cap
-constexpr double kPowerTol = 1e-7;    // relative change that ends it
 constexpr int kMaxBlockRows = 2048;   // n / 32 for n <= 65536
+
+// Number of eigenvalues of the symmetric tridiagonal matrix (diagonal a,
+// off-diagonal b, order m) below x: Sturm count of the LDL^T pivots.
+__device__ __forceinline__ int sturm_below(const double* a, const double* b,
+                                           int m, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (int i = 0; i < m; ++i) {
+    const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - x) - ((i > 0) ? bb / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Largest eigenvalue of the tridiagonal (a, b) of order m by multisection:
+// every thread counts at one point of the current bracket, and the bracket
+// shrinks to the two points around the top eigenvalue; five rounds of 256
+// points narrow a Gershgorin bracket by 256^5.
+__device__ double tridiag_top(const double* a, const double* b, int m,
+                              int* hits) {
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = ((i > 0) ? fabs(b[i - 1]) : 0.0) +
+                     ((i + 1 < m) ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  for (int round = 0; round < 5; ++round) {
+    const double h = (hi - lo) / kThreads;
+    const double x = lo + h * (threadIdx.x + 1);
+    // hits[t] = 1 when every eigenvalue lies below the point x_t
+    __syncthreads();
+    hits[threadIdx.x] = (sturm_below(a, b, m, x) == m) ? 1 : 0;
+    __syncthreads();
+    int first = kThreads - 1;   // smallest t with all eigenvalues below x_t
+    for (int t = 0; t < kThreads; ++t)
+      if (hits[t]) {
+        first = t;
+        break;
+      }
+    hi = lo + h * (first + 1);
+    lo = lo + h * first;
+  }
+  return 0.5 * (lo + hi);
+}
+
+constexpr int kLanczos = kLanczosMax;  // Krylov dimension cap
+constexpr double kLanczosTol = 1e-12; // relative change of the top Ritz value
 
 // Mixed norm of X~_{iter-1} - S (sec. 2): the spectral norm of the
 // symmetric, nonnegative matrix M of block Frobenius norms that the step's
-// epilogues wrote, i.e. its Perron root, by power iteration from the
-// all-ones vector with Rayleigh quotients x.Mx / x.x, in FP64. Every thread
-// of the workgroup takes part and receives the result.
-__device__ double mixed_norm(const Instance& in, int iter, double* x,
-                             double* y, double* red) {
+// epilogues wrote, i.e. its largest eigenvalue, by Lanczos from the
+// normalised all-ones vector with full reorthogonalisation (classical
+// Gram-Schmidt, twice), in FP64. The Lanczos basis lives in the instance's
+// scratch (kLanczos x nbk doubles); w is an LDS vector of nbk doubles, c an
+// LDS array of kLanczos doubles. Every thread of the workgroup takes part
+// and receives the result.
+__device__ double mixed_norm(const Instance& in, int iter, double* w,
+                             double* c, double* ta, double* tb, int* hits,
+                             double* red) {
   const int nb = in.nbk;
   const bool sparse = (in.brp[0] != nullptr);
   const int32_t* rp = sparse ? in.brp[iter & 1] : nullptr;
   const int32_t* col = sparse ? in.bcol[iter & 1] : nullptr;
-  for (int i = threadIdx.x; i < nb; i += kThreads) x[i] = 1.0;
-  double lam = 0.0;
-  for (int it = 0; it < kPowerIters; ++it) {
-    __syncthreads();
-    double xy = 0.0, xx = 0.0, yy = 0.0;
+  double* Q = in.lz;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double q0 = 1.0 / sqrt(static_cast<double>(nb));
+  for (int i = threadIdx.x; i < nb; i += kThreads) Q[i] = q0;
+  double theta = 0.0;
+  int m = 0;
+  for (int j = 0; j < kLanczos; ++j) {
+    __syncthreads();   // Q row j complete
+    const double* qj = Q + static_cast<size_t>(j) * nb;
     for (int i = threadIdx.x; i < nb; i += kThreads) {
       double acc = 0.0;
       if (sparse) {
         for (int q = rp[i]; q < rp[i + 1]; ++q)
-          acc += static_cast<double>(in.blk[q]) * x[col[q]];
+          acc += static_cast<double>(in.blk[q]) * qj[col[q]];
       } else {
         // M is symmetric: walk column i so that neighbouring threads read
         // neighbouring addresses
-        for (int j = 0; j < nb; ++j)
-          acc += static_cast<double>(in.blk[static_cast<size_t>(j) * nb + i]) *
-                 x[j];
+        for (int l = 0; l < nb; ++l)
+          acc += static_cast<double>(in.blk[static_cast<size_t>(l) * nb + i]) *
+                 qj[l];
       }
-      y[i] = acc;
-      xy += x[i] * acc;
-      xx += x[i] * x[i];
-      yy += acc * acc;
+      w[i] = acc;
     }
-    xy = block_sum_all(xy, red);
-    xx = block_sum_all(xx, red);
-    yy = block_sum_all(yy, red);
-    const double prev = lam;
-    lam = (xx > 0.0) ? xy / xx : 0.0;
-    if (!(yy > 0.0) || !isfinite(yy)) break;   // M = 0, or not finite
-    const double s = 1.0 / sqrt(yy);
-    for (int i = threadIdx.x; i < nb; i += kThreads) x[i] = y[i] * s;
-    if (it > 0 && fabs(lam - prev) <= kPowerTol * lam) break;
+    // w -= sum_l (q_l . w) q_l over l = 0..j, twice; the first pass's
+    // coefficient for l = j is alpha_j = q_j . M q_j
+    for (int pass = 0; pass < 2; ++pass) {
+      __syncthreads();
+      for (int l = wave; l <= j; l += kThreads / 64) {
+        const double* ql = Q + static_cast<size_t>(l) * nb;
+        double d = 0.0;
+        for (int i = lane; i < nb; i += 64) d += ql[i] * w[i];
+        d = wave_sum(d);
+        if (lane == 0) c[l] = d;
+      }
+      __syncthreads();
+      if (pass == 0 && threadIdx.x == 0) ta[j] = c[j];
+      for (int i = threadIdx.x; i < nb; i += kThreads) {
+        double x = w[i];
+        for (int l = 0; l <= j; ++l) x -= c[l] * Q[static_cast<size_t>(l) * nb + i];
+        w[i] = x;
+      }
+    }
+    double ww = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kThreads) ww += w[i] * w[i];
+    ww = block_sum_all(ww, red);
+    const double beta = sqrt(ww);
+    m = j + 1;
+    const double prev = theta;
+    theta = tridiag_top(ta, tb, m, hits);
+    // an invariant subspace (beta ~ 0), convergence, or the last step
+    if (!(beta > 1e-14 * fabs(theta)) || !isfinite(beta) ||
+        (j > 0 && fabs(theta - prev) <= kLanczosTol * fabs(theta)) ||
+        j + 1 == kLanczos || j + 1 == nb)
+      break;
+    __syncthreads();
+    if (threadIdx.x == 0) tb[j] = beta;
+    double* qn = Q + static_cast<size_t>(j + 1) * nb;
+    for (int i = threadIdx.x; i < nb; i += kThreads) qn[i] = w[i] / beta;
   }
-  return lam;
+  return theta;
 }
 
 __device__ __forceinline__ void publish(DevState* st, int32_t* ndone,
@@ -225,8 +304,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   const StopParams& prm = in.prm;
   double mk = 0.0;
   if (iter >= 1 && prm.norm == 1) {
-    __shared__ double xs[kMaxBlockRows], ys[kMaxBlockRows], red[kThreads / 64];
-    mk = mixed_norm(in, iter, xs, ys, red);
+    __shared__ double wv[kMaxBlockRows], cf[kLanczos], ta[kLanczos],
+        tb[kLanczos], red[kThreads / 64];
+    __shared__ int hits[kThreads];
+    mk = mixed_norm(in, iter, wv, cf, ta, tb, hits, red);
   }
   if (threadIdx.x != 0) return;
 

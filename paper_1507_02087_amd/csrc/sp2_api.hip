@@ -100,6 +100,8 @@ struct sp2_ctx_s {
   size_t d_sched_cap = 0;
   float* d_blk = nullptr;          // block norms of the mixed norm
   size_t d_blk_cap = 0;
+  double* d_lz = nullptr;          // Lanczos bases of the mixed norm
+  size_t d_lz_cap = 0;
   DevState* d_st = nullptr;
   size_t d_st_cap = 0;
   int2* d_tiles = nullptr;
@@ -353,15 +355,21 @@ sp2_status setup(sp2_ctx c) {
 
   // block norms of the mixed norm: an (np/32)^2 matrix per instance
   const bool mixed = (c->opt.norm == SP2_NORM_MIXED);
-  std::vector<size_t> blk_off(count, 0);
-  size_t blk_elems = 0;
+  std::vector<size_t> blk_off(count, 0), lz_off(count, 0);
+  size_t blk_elems = 0, lz_elems = 0;
   for (int b = 0; b < count; ++b) {
     blk_off[b] = blk_elems;
+    lz_off[b] = lz_elems;
     const size_t nbk = static_cast<size_t>(c->hi[b].np / sp2::kMixedBlock);
-    if (mixed) blk_elems += (nbk * nbk + 63) / 64 * 64;
+    if (mixed) {
+      blk_elems += (nbk * nbk + 63) / 64 * 64;
+      lz_elems += sp2::kLanczosMax * nbk;
+    }
   }
-  if (mixed)
+  if (mixed) {
     SP2_HIP(c, grow(c->d_blk, c->d_blk_cap, blk_elems * sizeof(float), s));
+    SP2_HIP(c, grow(c->d_lz, c->d_lz_cap, lz_elems * sizeof(double), s));
+  }
 
   // instance table, tiles and affine-start blocks
   SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
@@ -402,6 +410,7 @@ sp2_status setup(sp2_ctx c) {
     in.prm.norm = c->opt.norm;
     in.nbk = static_cast<int>(h.np / sp2::kMixedBlock);
     in.blk = mixed ? c->d_blk + blk_off[b] : nullptr;
+    in.lz = mixed ? c->d_lz + lz_off[b] : nullptr;
   }
 
   // launch groups: one per configuration in use (trivial instances stop
@@ -760,6 +769,7 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_inst);
   rel(c->d_sched);
   rel(c->d_blk);
+  rel(c->d_lz);
   rel(c->d_st);
   rel(c->d_tiles);
   rel(c->d_part);
@@ -985,6 +995,10 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
     SP2_HIP(c, grow(c->d_blk, c->d_blk_cap,
                     static_cast<size_t>(cap) * sizeof(float), s));
     in.blk = c->d_blk;
+    SP2_HIP(c, grow(c->d_lz, c->d_lz_cap,
+                    static_cast<size_t>(sp2::kLanczosMax) * nb * sizeof(double),
+                    s));
+    in.lz = c->d_lz;
     for (int k = 0; k < 2; ++k) {
       in.brp[k] = c->b.m[k].row_ptr;
       in.bcol[k] = c->b.m[k].col;

@@ -74,8 +74,10 @@ struct StopParams {
   int32_t pad;
 };
 
-// Edge of the blocks of the mixed norm (the block size of sec. 6).
+// Edge of the blocks of the mixed norm (the block size of sec. 6), and the
+// largest Krylov dimension used to find its spectral norm.
 constexpr int kMixedBlock = 32;
+constexpr int kLanczosMax = 64;
 
 // Step i's polynomial written in the square S = X~_{i-1}^2 that the step
 // computes: X_i = ca S + cb X~_{i-1} + cc I. Alg. 4: p = 1 expands
@@ -117,6 +119,7 @@ struct Instance {
   // block of the step's output pattern, whose row pointers and columns are
   // brp/bcol[i & 1] (nbk block rows).
   float* blk;
+  double* lz;        // Lanczos basis of the mixed norm: 64 x nbk doubles
   int nbk;
   int pad_blk;
   const int32_t* brp[2];
