@@ -345,6 +345,37 @@ sp2_status sp2_set_homo_lumo(sp2_ctx ctx, int32_t count,
                              const double* lumo_in, const double* lumo_out,
                              int32_t accelerate);
 
+/* ---------------------------------------------------------------------
+ * McWeeny and McW-ACC (sec. 3 of the paper).
+ *
+ * X_0 = (mu I - F) / gamma + I / 2 with gamma = 2 max(lambda_max - mu,
+ * mu - lambda_min); each step X_i = 3 X_s^2 - 2 X_s^3 with
+ * X_s = alpha_i (X~_{i-1} - I/2) + I/2, truncation as in SP2, and the stop
+ * at the first step k with log(e_k / 4) / log(e_{k-1}) < 1.8 (e = the
+ * Frobenius or mixed norm of X~_k - X~_k^2, evaluated when 0 < e_{k-1} < 1).
+ * Regular McWeeny: alpha = 1. McW-ACC with gap estimate xi:
+ * beta_0 = (1 - xi / gamma) / 2, alpha_i = 3 / sqrt(12 beta^2 - 18 beta + 9),
+ * beta_i = p_mw(alpha_i (beta_{i-1} - 1/2) + 1/2); the stretch is switched
+ * off (alpha = 1) once beta < 0.01 and the stop is tested from the step
+ * after (the Frobenius estimate can stop too early while it is on).
+ * Each step computes two products, S = X~^2 (which also gives e_{i-1}) and
+ * X~ S, and forms the new iterate from them in the second one's epilogue.
+ * --------------------------------------------------------------------- */
+
+/* Switches the instances of the last sp2_init_dense or sp2_batch_init to
+ * McWeeny for the following runs. mu (host array of count values) is the
+ * chemical potential of each instance, inside [lambda_min, lambda_max]; xi
+ * (host array, or NULL for the regular expansion) the McW-ACC gap
+ * estimates, each in (0, gamma]. n_occ of the init still selects the
+ * trivial cases 0 and n. sp2_get_info's n_squares counts steps (two
+ * products each); the history's p entries are 1. A later init returns the
+ * context to Alg. 2. Errors: SP2_BAD_STATE before an init, SP2_INVALID_ARG
+ * (count mismatch, NULL mu, values out of range (the message names the
+ * instance), block-sparse contexts, a context with an SP2-ACC schedule),
+ * SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. */
+sp2_status sp2_set_mcweeny(sp2_ctx ctx, int32_t count, const double* mu,
+                           const double* xi);
+
 /* Installs a table that chooses the square-kernel configuration per
  * instance when opt->kernel_config is 0: for an instance of dimension n and
  * precision p, the first entry e (in the given order) with precision[e] == p

@@ -72,6 +72,7 @@ SIGNATURES = {
                                                       _c.c_void_p, _c.c_void_p]),
     "sp2_set_homo_lumo": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
                                      _c.c_void_p, _c.c_void_p, _c.c_int32]),
+    "sp2_set_mcweeny": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p]),
     "sp2_batch_get_run_time": (_c.c_int, [_c.c_void_p, _c.POINTER(_c.c_double),
                                           _c.POINTER(_c.c_int32)]),
     "sp2_set_kernel_table": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p,
@@ -289,6 +290,20 @@ class Context:
                                                 1 if accelerate else 0),
                     "sp2_set_homo_lumo")
 
+    def set_mcweeny(self, mu, xi=None):
+        """Switches the instances of the last init to McWeeny (xi None) or
+        McW-ACC with gap estimate xi (sec. 3): scalars for a dense context,
+        sequences (one entry per instance) for a batch."""
+        if isinstance(mu, (int, float)):
+            mu = [mu]
+            xi = None if xi is None else [xi]
+        mus = _arr(ctypes.c_double, [float(x) for x in mu])
+        xis = None if xi is None else _arr(ctypes.c_double, [float(x) for x in xi])
+        if xi is not None and len(xi) != len(mu):
+            raise ValueError("mu and xi differ in length")
+        self._check(self._lib.sp2_set_mcweeny(self._h, len(mu), mus, xis),
+                    "sp2_set_mcweeny")
+
     def get_mixed_history(self, index: int = 0):
         """m[k] = mixed norm of X~_k - X~_k^2 of the last run (norm="mixed")."""
         import numpy as np
@@ -470,7 +485,8 @@ class BatchContext(Context):
 
 
 def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None,
-              as_fp64: bool = True, homo_lumo=None, accelerate: bool = True, **opts):
+              as_fp64: bool = True, homo_lumo=None, accelerate: bool = True,
+              mcweeny=None, **opts):
     """SP2 on many independent matrices at once; returns (results, run_ms).
     homo_lumo = four sequences (homo_out, homo_in, lumo_in, lumo_out) with one
     entry per matrix selects SP2-ACC (Alg. 3/4)."""
@@ -481,6 +497,8 @@ def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None
         ctx.batch_init(Fs, lambda_min, lambda_max, n_occ, **opts)
         if homo_lumo is not None:
             ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
+        if mcweeny is not None:
+            ctx.set_mcweeny(*mcweeny)
         ctx.batch_run()
         ms, _ = ctx.batch_run_time()
         out = []
@@ -500,9 +518,11 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
               trunc_tau: float = 0.0, max_iter: int = 100,
               kernel_config: int = 0, tail_split: int = 0,
               as_fp64: bool = True, ctx: Context | None = None,
-              homo_lumo=None, accelerate: bool = True, norm: str = "fro") -> Result:
+              homo_lumo=None, accelerate: bool = True, norm: str = "fro",
+              mcweeny=None) -> Result:
     """SP2 (Alg. 2) on the GPU from F to the converged density matrix; with
-    homo_lumo = (homo_out, homo_in, lumo_in, lumo_out), SP2-ACC (Alg. 3/4)."""
+    homo_lumo = (homo_out, homo_in, lumo_in, lumo_out), SP2-ACC (Alg. 3/4);
+    with mcweeny = (mu, xi or None), McWeeny / McW-ACC (sec. 3)."""
     own = ctx is None
     if own:
         ctx = Context(F.device.index or 0)
@@ -511,6 +531,8 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
                        trunc_tau, max_iter, kernel_config, tail_split, norm=norm)
         if homo_lumo is not None:
             ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
+        if mcweeny is not None:
+            ctx.set_mcweeny(*mcweeny)
         st = ctx.run()
         D = ctx.get_density(as_fp64=as_fp64)
         n, sq, ms = ctx.get_info()

@@ -17,6 +17,10 @@ __device__ __forceinline__ double c_sp2() {
 }
 // q~ of sec. 2.
 constexpr double kQTilde = 1.8;
+// sec. 3: C_2 of the McWeeny and McW-ACC expansions, and the beta below
+// which McW-ACC switches its stretch off.
+constexpr double kCMcWeeny = 4.0;
+constexpr double kMwDelta = 0.01;
 
 __device__ __forceinline__ double wave_sum(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -312,6 +316,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   if (threadIdx.x != 0) return;
 
   const bool sched = prm.n_max > 0;
+  const bool mw = (prm.method == 1);
   const double t1 = b, t2 = c;
   st->t1[iter] = t1;
   st->t2[iter] = t2;
@@ -334,7 +339,14 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     const double* e = (prm.norm == 1) ? st->m : st->v;
     const double ek = e[k];
     double r = NAN;
-    if (k >= 2) {
+    if (mw) {
+      // McWeeny: one polynomial per step, C = 4 (sec. 3)
+      if (k >= 1) {
+        const double ekm1 = e[k - 1];
+        if (ekm1 > 0.0 && ekm1 < 1.0 && ek > 0.0)
+          r = log(ek / kCMcWeeny) / log(ekm1);
+      }
+    } else if (k >= 2) {
       const double ekm2 = e[k - 2];
       if (ekm2 > 0.0 && ekm2 < 1.0 && ek > 0.0)
         r = log(ek / c_sp2()) / log(ekm2);   // observed order (sec. 2)
@@ -348,10 +360,17 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
       publish(st, ndone, count, mirror, 0, k);
       return;
     }
-    const int kmin = sched ? prm.n_min : 2;
-    if (k >= kmin && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
-      publish(st, ndone, count, mirror, 0, k);   // Alg. 2 / Alg. 4 stop
-      return;
+    if (mw) {
+      if (st->mw_first > 0 && k >= st->mw_first && !isnan(r) && r < kQTilde) {
+        publish(st, ndone, count, mirror, 0, k);   // McWeeny stop (sec. 3)
+        return;
+      }
+    } else {
+      const int kmin = sched ? prm.n_min : 2;
+      if (k >= kmin && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
+        publish(st, ndone, count, mirror, 0, k);   // Alg. 2 / Alg. 4 stop
+        return;
+      }
     }
     if (sched && k >= prm.n_max) {               // the schedule has ended
       publish(st, ndone, count, mirror, 0, k);
@@ -369,9 +388,30 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   // Polynomial of the next step: from the schedule (Alg. 4), or from the
   // traces of X~_iter (Alg. 2 branch). Past the schedule's end one more
   // square is needed for v_{n_max}; the iterate it yields is not used.
+  // McWeeny: the stretch of McW-ACC from beta, switched off (and the stop
+  // enabled from the step after) once beta < 0.01; the regular expansion
+  // tests the stop from step 1.
   int pn;
   double an = 1.0;
-  if (sched) {
+  if (mw) {
+    if (iter == 0) {
+      st->mw_beta = prm.mw_beta0;
+      st->mw_stretch = prm.mw_acc;
+      st->mw_first = prm.mw_acc ? 0 : 1;
+    }
+    const int i = iter + 1;
+    if (st->mw_stretch && st->mw_beta < kMwDelta) {
+      st->mw_stretch = 0;
+      st->mw_first = i + 1;
+    }
+    pn = 1;
+    if (st->mw_stretch) {
+      const double be = st->mw_beta;
+      an = 3.0 / sqrt(12.0 * be * be - 18.0 * be + 9.0);
+      const double bs = an * (be - 0.5) + 0.5;
+      st->mw_beta = 3.0 * bs * bs - 2.0 * bs * bs * bs;
+    }
+  } else if (sched) {
     const int i = iter + 1;
     if (i <= prm.n_max) {
       pn = in.sched_p[i];

@@ -93,6 +93,12 @@ struct sp2_ctx_s {
   size_t pool_cap[2] = {0, 0};
   void* split_pool[4] = {nullptr, nullptr, nullptr, nullptr};   // H0 L0 H1 L1
   size_t split_cap[4] = {0, 0, 0, 0};
+  // McWeeny: the square S of every instance, and its split (BF16x3)
+  void* s_pool = nullptr;
+  size_t s_pool_cap = 0;
+  void* s_split[2] = {nullptr, nullptr};
+  size_t s_split_cap[2] = {0, 0};
+  bool mcweeny = false;
   Instance* d_inst = nullptr;
   size_t d_inst_cap = 0;
   std::vector<Instance> h_inst;    // host copy of the instance table
@@ -472,6 +478,7 @@ sp2_status setup(sp2_ctx c) {
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, inst.data(), count * sizeof(Instance),
                             hipMemcpyHostToDevice, s));
   c->h_inst = inst;
+  c->mcweeny = false;
   if (!tiles.empty())
     SP2_HIP(c, hipMemcpyAsync(c->d_tiles, tiles.data(),
                               tiles.size() * sizeof(int2),
@@ -512,6 +519,7 @@ sp2_status run_batch(sp2_ctx c) {
   SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
 
   sp2::SquareArgs a;
+  a.mode = 0;
   a.inst = c->d_inst;
   a.tiles = c->d_tiles;
   a.ws = c->d_ws;
@@ -537,12 +545,18 @@ sp2_status run_batch(sp2_ctx c) {
                                          static_cast<int>(c->b.n), c->d_part,
                                          c->b.grid, s));
     }
-    for (const Group& g : c->groups) {
-      a.items = g.items;
-      a.tails = g.tails;
-      a.ntail = g.ntail;
-      a.split = g.split;
-      SP2_HIP(c, sp2::launch_square(g.cfg, a, g.grid, s));
+    // one square per group (Alg. 2 / Alg. 4); McWeeny: the square S of
+    // every group, then X~ S of every group (the groups share the workspace)
+    const int nmodes = c->mcweeny ? 2 : 1;
+    for (int mi = 0; mi < nmodes; ++mi) {
+      a.mode = c->mcweeny ? mi + 1 : 0;
+      for (const Group& g : c->groups) {
+        a.items = g.items;
+        a.tails = g.tails;
+        a.ntail = g.ntail;
+        a.split = g.split;
+        SP2_HIP(c, sp2::launch_square(g.cfg, a, g.grid, s));
+      }
     }
     if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i + 1], s));
     SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
@@ -770,6 +784,9 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_sched);
   rel(c->d_blk);
   rel(c->d_lz);
+  rel(c->s_pool);
+  rel(c->s_split[0]);
+  rel(c->s_split[1]);
   rel(c->d_st);
   rel(c->d_tiles);
   rel(c->d_part);
@@ -1011,6 +1028,7 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
                             hipMemcpyHostToDevice, s));
   SP2_HIP(c, hipStreamSynchronize(s));
   c->h_inst.assign(1, in);
+  c->mcweeny = false;
   release_groups(c);
   HostInst h;
   h.F = nullptr;
@@ -1145,6 +1163,68 @@ sp2_status sp2_get_info(sp2_ctx c, int32_t* n_iter, int32_t* n_squares,
   return SP2_OK;
 }
 
+sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
+                           const double* xi) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->inited)
+    return fail(c, SP2_BAD_STATE, "no instances: call an init first",
+                hipSuccess);
+  if (c->bsr)
+    return fail(c, SP2_INVALID_ARG,
+                "McWeeny needs a general product; not available for "
+                "block-sparse contexts",
+                hipSuccess);
+  if (count != static_cast<int32_t>(c->hi.size()) || !mu)
+    return fail(c, SP2_INVALID_ARG,
+                "count must equal the number of instances; mu must be given",
+                hipSuccess);
+  if (c->h_inst.size() && c->h_inst[0].prm.n_max > 0)
+    return fail(c, SP2_INVALID_ARG,
+                "an SP2-ACC schedule is set: re-initialise first", hipSuccess);
+  for (int b = 0; b < count; ++b) {
+    const HostInst& h = c->hi[b];
+    const double gam = 2.0 * std::max(h.lmax - mu[b], mu[b] - h.lmin);
+    const bool ok_mu = isfinite(mu[b]) && mu[b] >= h.lmin && mu[b] <= h.lmax;
+    const bool ok_xi = !xi || (isfinite(xi[b]) && xi[b] > 0.0 && xi[b] <= gam);
+    if (!ok_mu || !ok_xi || !(gam > 0.0)) {
+      c->err = "instance " + std::to_string(b) +
+               ": mu outside [lambda_min, lambda_max] or xi outside (0, gamma]";
+      return SP2_INVALID_ARG;
+    }
+  }
+  SP2_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = c->stream;
+  size_t pool_elems = 0;
+  for (const HostInst& h : c->hi)
+    pool_elems = std::max(pool_elems,
+                          h.xoff + static_cast<size_t>(h.np) * h.np);
+  const size_t esz = c->fp64_store ? 8 : 4;
+  SP2_HIP(c, grow(c->s_pool, c->s_pool_cap, pool_elems * esz, s));
+  const bool split = (c->opt.precision == SP2_BF16X3);
+  if (split)
+    for (int q = 0; q < 2; ++q)
+      SP2_HIP(c, grow(c->s_split[q], c->s_split_cap[q], pool_elems * 2, s));
+  for (int b = 0; b < count; ++b) {
+    const HostInst& h = c->hi[b];
+    Instance& in = c->h_inst[b];
+    const double gam = 2.0 * std::max(h.lmax - mu[b], mu[b] - h.lmin);
+    // X_0 = (mu I - F) / gamma + I / 2 = ((mu + gamma / 2) I - F) / gamma
+    in.lmax = mu[b] + 0.5 * gam;
+    in.width = gam;
+    in.S = static_cast<char*>(c->s_pool) + h.xoff * esz;
+    in.SH = split ? static_cast<char*>(c->s_split[0]) + h.xoff * 2 : nullptr;
+    in.SL = split ? static_cast<char*>(c->s_split[1]) + h.xoff * 2 : nullptr;
+    in.prm.method = 1;
+    in.prm.mw_acc = xi ? 1 : 0;
+    in.prm.mw_beta0 = xi ? 0.5 * (1.0 - xi[b] / gam) : 0.0;
+  }
+  SP2_HIP(c, hipMemcpyAsync(c->d_inst, c->h_inst.data(),
+                            count * sizeof(Instance), hipMemcpyHostToDevice, s));
+  SP2_HIP(c, hipStreamSynchronize(s));
+  c->mcweeny = true;
+  return SP2_OK;
+}
+
 sp2_status sp2_get_mixed_history(sp2_ctx c, int32_t index, int32_t cap,
                                  int32_t* len, double* m) {
   if (!c) return SP2_INVALID_ARG;
@@ -1176,6 +1256,9 @@ sp2_status sp2_set_homo_lumo(sp2_ctx c, int32_t count, const double* homo_out,
                 hipSuccess);
   if (!homo_out || !homo_in || !lumo_in || !lumo_out)
     return fail(c, SP2_INVALID_ARG, "NULL bound array", hipSuccess);
+  if (c->mcweeny)
+    return fail(c, SP2_INVALID_ARG,
+                "the context runs McWeeny: re-initialise first", hipSuccess);
   SP2_HIP(c, hipSetDevice(c->device));
   const int L = sp2::kMaxIter + 2;   // entries 1..n_max are used
   std::vector<double> alpha(static_cast<size_t>(count) * L, 1.0);

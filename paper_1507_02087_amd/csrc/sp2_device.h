@@ -48,6 +48,11 @@ struct DevState {
   double alpha[kMaxIter + 2];
   double v[kMaxIter + 1];
   double m[kMaxIter + 1];   // mixed norm ||X~_k - X~_k^2||_M (mixed mode)
+  // McWeeny (sec. 3): the stretch's beta, whether the stretch is on, and
+  // the first step whose error the stop may test (0: none yet)
+  double mw_beta;
+  int32_t mw_stretch;
+  int32_t mw_first;
   double t1[kMaxIter + 2];
   double t2[kMaxIter + 2];
   double r[kMaxIter + 1];
@@ -71,8 +76,24 @@ struct StopParams {
   int32_t n_min;     // schedule: first step where the stop is tested
   int32_t n_max;     // schedule length; 0 = no schedule (Alg. 2 branch)
   int32_t norm;      // error fed to the stop: 0 Frobenius, 1 mixed
+  int32_t method;    // 0 SP2 (Alg. 2, or Alg. 4 with a schedule), 1 McWeeny
+  int32_t mw_acc;    // McWeeny: 1 = McW-ACC with mw_beta0
   int32_t pad;
+  double mw_beta0;   // McW-ACC: 0.5 (1 - xi / gamma)
 };
+
+// McWeeny step written in the two products it computes, S = X~^2 and
+// T = X~ S: with X_s = a (X~ - I/2) + I/2 and b = (1 - a)/2,
+// 3 X_s^2 - 2 X_s^3 = c3 T + c2 S + c1 X~ + c0 I (sec. 3, Alg. McW-ACC);
+// a = 1 gives 3 S - 2 T.
+struct MwCoef {
+  double c3, c2, c1, c0;
+};
+__host__ __device__ __forceinline__ MwCoef mw_coef(double a) {
+  const double b = 0.5 * (1.0 - a);
+  return MwCoef{-2.0 * a * a * a, 3.0 * a * a - 6.0 * a * a * b,
+                6.0 * a * b - 6.0 * a * b * b, 3.0 * b * b - 2.0 * b * b * b};
+}
 
 // Edge of the blocks of the mixed norm (the block size of sec. 6), and the
 // largest Krylov dimension used to find its spectral norm.
@@ -100,6 +121,11 @@ struct Instance {
   // kernel families that read them (null otherwise)
   void* XH[2];
   void* XL[2];
+  // McWeeny only: the square S = X~^2 of the step (same layout as X) and
+  // its BF16x3 split (null otherwise)
+  void* S;
+  void* SH;
+  void* SL;
   const double* F;     // input, FP64, row-major
   int64_t ldf;
   int n;               // matrix dimension
@@ -183,6 +209,7 @@ struct SquareArgs {
   int ntail;                  // tail tiles (0: no tail launch)
   int split;                  // pieces per tail tile
   int iter;                   // step i: X~_{i-1} -> X~_i
+  int mode;                   // 0 SP2 step; McWeeny: 1 S = X~^2, 2 T = X~ S
   double* part;   // 3 doubles per tile (global slot): ||X - S||_F^2, Tr, sum x^2
 };
 

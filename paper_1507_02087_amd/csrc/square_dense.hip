@@ -47,8 +47,11 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Writes the tile's three partial sums in a fixed order (deterministic).
+// mode 1 (McWeeny square) writes only the error, mode 2 (McWeeny product
+// X~ S) only the traces, so that the two products of a step fill one slot.
 template <int THREADS>
-__device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
+__device__ __forceinline__ void store_partials(Sums s, double* part, int slot,
+                                               int mode = 0) {
   __shared__ double sh[THREADS / 64][3];
   s.v = wave_sum(s.v);
   s.t1 = wave_sum(s.t1);
@@ -67,16 +70,22 @@ __device__ __forceinline__ void store_partials(Sums s, double* part, int slot) {
       b += sh[w][1];
       c += sh[w][2];
     }
-    part[3 * slot + 0] = a;
-    part[3 * slot + 1] = b;
-    part[3 * slot + 2] = c;
+    if (mode != 2) part[3 * slot + 0] = a;
+    if (mode != 1) {
+      part[3 * slot + 1] = b;
+      part[3 * slot + 2] = c;
+    }
   }
 }
 
-// Step polynomial in the storage type: X_i = ca S + cb X~ + cc I.
+// Step polynomial in the storage type. mode 0 (SP2 step): X_i = ca S +
+// cb X~ + cc I from the square S. mode 1 (McWeeny, first product): the
+// square itself is the output. mode 2 (McWeeny, second product T = X~ S):
+// X_i = ca T + cs S + cb X~ + cc I.
 template <typename T>
 struct Coef {
-  T ca, cb, cc;
+  T ca, cb, cc, cs;
+  int mode;
 };
 
 __device__ __forceinline__ double fused(double a, double b, double c) {
@@ -92,14 +101,22 @@ __device__ __forceinline__ float fused(float a, float b, float c) {
 // must stay zero under the identity term). With the
 // coefficients of Alg. 2 (1, 0, 0) and (-1, 2, 0) the new value is exactly S
 // and the single rounding of 2 X~ - S.
-template <typename T>
-__device__ __forceinline__ T epilogue_elem(T s, T xo, const Coef<T>& k,
+template <typename T, int MODE>
+__device__ __forceinline__ T epilogue_elem(T s, T xo, T sv, const Coef<T>& k,
                                            double tau, double w, bool on_diag,
                                            Sums& acc, double& d2) {
-  const double d = static_cast<double>(xo) - static_cast<double>(s);
-  d2 = d * d;
-  acc.v += w * d2;
-  T xn = fused(k.cb, xo, k.ca * s);
+  T xn;
+  if (MODE == 2) {
+    // s = (X~ S)_ij, sv = S_ij: the new iterate, no error term
+    d2 = 0.0;
+    xn = fused(k.ca, s, fused(k.cs, sv, k.cb * xo));
+  } else {
+    const double d = static_cast<double>(xo) - static_cast<double>(s);
+    d2 = d * d;
+    acc.v += w * d2;
+    if (MODE == 1) return s;   // the square S, kept as it is
+    xn = fused(k.cb, xo, k.ca * s);
+  }
   if (on_diag) xn += k.cc;
   double xd = static_cast<double>(xn);
   if (fabs(xd) < tau) {
@@ -130,8 +147,9 @@ __device__ __forceinline__ void blk_write(float* blk, int nbk, int rb, int cb,
 // Applies the epilogue to one accumulator value at tile-local (lr, lc);
 // returns the element's share of its block's squared norm (0 if the element
 // is a mirrored one that this tile does not process).
-template <typename T>
+template <typename T, int MODE>
 __device__ __forceinline__ double epilogue_at(const T* __restrict__ X,
+                                              const T* __restrict__ Sr,
                                               T* __restrict__ Y, int ld, int n,
                                               int I, int J, int BM, int lr,
                                               int lc, T s, const Coef<T>& k,
@@ -139,16 +157,17 @@ __device__ __forceinline__ double epilogue_at(const T* __restrict__ X,
   const int gr = I * BM + lr, gc = J * BM + lc;
   const size_t idx = static_cast<size_t>(gr) * ld + gc;
   double d2 = 0.0;
+  const T sv = (MODE == 2) ? *gro(Sr + idx) : T(0);
   if (I != J) {
-    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, 2.0, false, sums,
-                                  d2);
+    const T xn = epilogue_elem<T, MODE>(s, *gro(X + idx), sv, k, tau, 2.0, false,
+                                  sums, d2);
     *grw(Y + idx) = xn;
     *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
     return d2;
   } else if (gr <= gc) {
     const bool on = (gr == gc);
-    const T xn = epilogue_elem<T>(s, *gro(X + idx), k, tau, on ? 1.0 : 2.0,
-                                  on && gr < n, sums, d2);
+    const T xn = epilogue_elem<T, MODE>(s, *gro(X + idx), sv, k, tau,
+                                  on ? 1.0 : 2.0, on && gr < n, sums, d2);
     *grw(Y + idx) = xn;
     if (!on) *grw(Y + static_cast<size_t>(gc) * ld + gr) = xn;
     return block_share(gr, gc, d2);
@@ -197,11 +216,15 @@ struct Stage {
 // What one workgroup needs to know about its step, built at kernel start.
 template <typename T>
 struct StepCtx {
-  const T* X;     // X~_{i-1}
-  T* Y;           // X~_i
+  const T* X;     // X~_{i-1}: A operand rows, and the epilogue's X~
+  const T* B;     // B operand rows: X~ (a square) or S (McWeeny X~ S)
+  const T* Sr;    // S for the McWeeny X~ S epilogue (null otherwise)
+  T* Y;           // output: X~_i, or S for the McWeeny square
   const __bf16* Xh;   // BF16x3 split of X~_{i-1} (null if absent)
   const __bf16* Xl;
-  __bf16* Yh;         // BF16x3 split of X~_i (null if absent)
+  const __bf16* Bh;   // BF16x3 split of the B operand
+  const __bf16* Bl;
+  __bf16* Yh;         // BF16x3 split of the output (null if absent)
   __bf16* Yl;
   int ld;
   int n;          // matrix dimension (rows and columns >= n are padding)
@@ -217,20 +240,39 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
                                                const Instance& in, int slot) {
   StepCtx<T> c;
   c.X = static_cast<const T*>(in.X[(a.iter - 1) & 1]);
-  c.Y = static_cast<T*>(in.X[a.iter & 1]);
   c.Xh = static_cast<const __bf16*>(in.XH[(a.iter - 1) & 1]);
   c.Xl = static_cast<const __bf16*>(in.XL[(a.iter - 1) & 1]);
-  c.Yh = static_cast<__bf16*>(in.XH[a.iter & 1]);
-  c.Yl = static_cast<__bf16*>(in.XL[a.iter & 1]);
   c.ld = in.ld;
   c.n = in.n;
   c.tile = a.tiles[slot];
-  const StepCoef sc = step_coef(in.st->p[a.iter], in.st->alpha[a.iter]);
-  c.k = Coef<T>{static_cast<T>(sc.ca), static_cast<T>(sc.cb),
-                static_cast<T>(sc.cc)};
   c.tau = in.tau;
   c.blk = in.blk;
   c.nbk = in.nbk;
+  c.Sr = nullptr;
+  if (a.mode == 0) {
+    const StepCoef sc = step_coef(in.st->p[a.iter], in.st->alpha[a.iter]);
+    c.k = Coef<T>{static_cast<T>(sc.ca), static_cast<T>(sc.cb),
+                  static_cast<T>(sc.cc), T(0), 0};
+  } else if (a.mode == 1) {
+    c.k = Coef<T>{T(1), T(0), T(0), T(0), 1};
+    c.tau = 0.0;   // S is not an iterate: no truncation
+  } else {
+    const MwCoef mc = mw_coef(in.st->alpha[a.iter]);
+    c.k = Coef<T>{static_cast<T>(mc.c3), static_cast<T>(mc.c1),
+                  static_cast<T>(mc.c0), static_cast<T>(mc.c2), 2};
+    c.blk = nullptr;   // the block norms came from the square
+  }
+  // operands: X~ X~ for a square, X~ S for McWeeny's second product
+  c.B = (a.mode == 2) ? static_cast<const T*>(in.S) : c.X;
+  c.Bh = (a.mode == 2) ? static_cast<const __bf16*>(in.SH) : c.Xh;
+  c.Bl = (a.mode == 2) ? static_cast<const __bf16*>(in.SL) : c.Xl;
+  if (a.mode == 2) c.Sr = static_cast<const T*>(in.S);
+  // output: S for McWeeny's square, the next iterate otherwise
+  c.Y = (a.mode == 1) ? static_cast<T*>(in.S) : static_cast<T*>(in.X[a.iter & 1]);
+  c.Yh = (a.mode == 1) ? static_cast<__bf16*>(in.SH)
+                       : static_cast<__bf16*>(in.XH[a.iter & 1]);
+  c.Yl = (a.mode == 1) ? static_cast<__bf16*>(in.SL)
+                       : static_cast<__bf16*>(in.XL[a.iter & 1]);
   return c;
 }
 
@@ -276,7 +318,7 @@ __device__ __forceinline__ void mainloop_f64(const StepCtx<double>& sc,
   const int ld = sc.ld;
   const T* X = sc.X;
   const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
-  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const T* Bp = sc.B + static_cast<size_t>(tt.y * C::BM) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 15, g = lane >> 4;
@@ -326,7 +368,7 @@ __device__ __forceinline__ void mainloop_f64(const StepCtx<double>& sc,
   }
 }
 
-template <class C>
+template <class C, int MODE>
 __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
                                              double* part, int slot,
                                              const typename C::Acc& acc) {
@@ -347,8 +389,8 @@ __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        bs[m / 2][n / 2] += epilogue_at<T>(
-            X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
+        bs[m / 2][n / 2] += epilogue_at<T, MODE>(
+            X, sc.Sr, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
             wm + m * 16 + (lane >> 4) + 4 * j, wn + n * 16 + (lane & 15),
             acc.c[m][n][j], sc.k, sc.tau, sums);
   if (sc.blk) {
@@ -362,7 +404,7 @@ __device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
         if (lane == 0 && rb <= cb) blk_write(sc.blk, sc.nbk, rb, cb, t);
       }
   }
-  store_partials<C::THREADS>(sums, part, slot);
+  store_partials<C::THREADS>(sums, part, slot, MODE);
 }
 
 // ============================================================== FP32
@@ -394,7 +436,7 @@ __device__ __forceinline__ void mainloop_f32(const StepCtx<float>& sc,
   const int ld = sc.ld;
   const T* X = sc.X;
   const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
-  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const T* Bp = sc.B + static_cast<size_t>(tt.y * C::BM) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 31, h = lane >> 5;
@@ -440,7 +482,7 @@ __device__ __forceinline__ void mainloop_f32(const StepCtx<float>& sc,
   }
 }
 
-template <class C>
+template <class C, int MODE>
 __device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
                                              double* part, int slot,
                                              const typename C::Acc& acc) {
@@ -459,18 +501,18 @@ __device__ __forceinline__ void epilogue_f32(const StepCtx<float>& sc,
       double bs = 0.0;
 #pragma unroll
       for (int j = 0; j < 16; ++j)
-        bs += epilogue_at<T>(
-            X, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
+        bs += epilogue_at<T, MODE>(
+            X, sc.Sr, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
             wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3),
             wn + n * 32 + (lane & 31), acc.c[m][n][j], sc.k, sc.tau, sums);
-      if (sc.blk) {
+      if (MODE != 2 && sc.blk) {
         const double t = full_wave_sum(bs);
         const int rb = (tt.x * C::BM + wm) / kMixedBlock + m;
         const int cb = (tt.y * C::BM + wn) / kMixedBlock + n;
         if (lane == 0 && rb <= cb) blk_write(sc.blk, sc.nbk, rb, cb, t);
       }
     }
-  store_partials<C::THREADS>(sums, part, slot);
+  store_partials<C::THREADS>(sums, part, slot, MODE);
 }
 
 // ============================================================== BF16x3
@@ -515,7 +557,7 @@ __device__ __forceinline__ void mainloop_b3(const StepCtx<float>& sc,
   const int ld = sc.ld;
   const T* X = sc.X;
   const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
-  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const T* Bp = sc.B + static_cast<size_t>(tt.y * C::BM) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 31, h = lane >> 5;
@@ -623,7 +665,7 @@ __device__ __forceinline__ void mainloop_b3s(const StepCtx<float>& sc,
   const int ld = sc.ld;
   const T* X = sc.X;
   const T* Ap = X + static_cast<size_t>(tt.x * C::BM) * ld;
-  const T* Bp = X + static_cast<size_t>(tt.y * C::BM) * ld;
+  const T* Bp = sc.B + static_cast<size_t>(tt.y * C::BM) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 31, h = lane >> 5;
@@ -737,7 +779,7 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   const size_t ao = static_cast<size_t>(tt.x * C::BM) * ld;
   const size_t bo = static_cast<size_t>(tt.y * C::BM) * ld;
   const __bf16 *Ah = sc.Xh + ao, *Al = sc.Xl + ao;
-  const __bf16 *Bh = sc.Xh + bo, *Bl = sc.Xl + bo;
+  const __bf16 *Bh = sc.Bh + bo, *Bl = sc.Bl + bo;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
   const int r = lane & 31, h = lane >> 5;
@@ -818,7 +860,7 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
 // threads apply the element epilogue in row order (coalesced reads of X and
 // writes of the tile) and write the transposed band in row order of the
 // transpose (coalesced), reading LDS down columns (padding: no conflicts).
-template <class C>
+template <class C, int MODE>
 __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
                                                  double* part, int slot,
                                                  const typename C::Acc& acc,
@@ -870,7 +912,8 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
           const size_t idx = static_cast<size_t>(gr) * ld + gc;
           const bool on = (gr == gc);
           double d2;
-          const T xn = epilogue_elem<T>(S[rr * LD + cc], *gro(sc.X + idx),
+          const T sv = (MODE == 2) ? *gro(sc.Sr + idx) : T(0);
+          const T xn = epilogue_elem<T, MODE>(S[rr * LD + cc], *gro(sc.X + idx), sv,
                                         sc.k, sc.tau, on ? 1.0 : 2.0,
                                         on && gr < sc.n, sums, d2);
           *grw(sc.Y + idx) = xn;
@@ -903,7 +946,7 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       if (split) store_split(sc.Yh, sc.Yl, idt, xn);
     }
   }
-  store_partials<C::THREADS>(sums, part, slot);
+  store_partials<C::THREADS>(sums, part, slot, MODE);
 }
 
 // ============================================================== drivers
@@ -951,9 +994,10 @@ struct Ops<CfgF64<A, B, Cc, D>> {
                               typename C::Acc& acc, char*) {
     mainloop_f64<C>(sc, w, acc);
   }
+  template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char*) {
-    epilogue_f64<C>(sc, part, slot, acc);
+    epilogue_f64<C, MODE>(sc, part, slot, acc);
   }
 };
 
@@ -966,9 +1010,10 @@ struct Ops<CfgF32<A, B, Cc, D>> {
                               typename C::Acc& acc, char*) {
     mainloop_f32<C>(sc, w, acc);
   }
+  template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char*) {
-    epilogue_f32<C>(sc, part, slot, acc);
+    epilogue_f32<C, MODE>(sc, part, slot, acc);
   }
 };
 
@@ -982,9 +1027,10 @@ struct Ops<CfgB3<A, B, Cc, D>> {
     mainloop_b3<C>(sc, w, acc);
   }
   // The BF16x3 accumulators have the FP32 32x32 layout.
+  template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char*) {
-    epilogue_f32<C>(sc, part, slot, acc);
+    epilogue_f32<C, MODE>(sc, part, slot, acc);
   }
 };
 
@@ -997,9 +1043,10 @@ struct Ops<CfgB3S<A, B, Cc, D>> {
                               typename C::Acc& acc, char* smem) {
     mainloop_b3s<C>(sc, w, acc, smem);
   }
+  template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C>(sc, part, slot, acc, smem);
+    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
@@ -1012,13 +1059,14 @@ struct Ops<CfgB3P<A, B, Cc, D>> {
                               typename C::Acc& acc, char* smem) {
     mainloop_b3p<C>(sc, w, acc, smem);
   }
+  template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C>(sc, part, slot, acc, smem);
+    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
-template <class C>
+template <class C, int MODE>
 __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
   const WorkItem w = a.items[blockIdx.x];
@@ -1030,7 +1078,7 @@ __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   typename C::Acc acc;
   Ops<C>::main(sc, w, acc, smem);
   if (w.piece < 0) {
-    Ops<C>::epi(sc, a.part, w.slot, acc, smem);
+    Ops<C>::template epi<MODE>(sc, a.part, w.slot, acc, smem);
   } else {
     ws_store<C>(acc, static_cast<T*>(a.ws) +
                          static_cast<size_t>(w.piece) * C::BM * C::BM);
@@ -1038,7 +1086,7 @@ __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
 }
 
 // Sums the pieces of tail tile blockIdx.x in piece order, then the epilogue.
-template <class C>
+template <class C, int MODE>
 __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
   const TailItem t = a.tails[blockIdx.x];
@@ -1052,7 +1100,7 @@ __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   for (int j = 0; j < a.split; ++j)
     ws_accumulate<C>(acc, ws + static_cast<size_t>(t.piece0 + j) *
                                    C::BM * C::BM);
-  Ops<C>::epi(sc, a.part, t.slot, acc, smem);
+  Ops<C>::template epi<MODE>(sc, a.part, t.slot, acc, smem);
 }
 
 // Kernel configurations: macro tile, waves (M x N), K slice.
@@ -1072,14 +1120,27 @@ using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
 using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
 using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
 
-template <class C>
-hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(square_kernel<C>, dim3(grid), dim3(C::THREADS), 0, s, a);
+template <class C, int MODE>
+hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((square_kernel<C, MODE>), dim3(grid), dim3(C::THREADS), 0,
+                     s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ntail == 0) return e;
-  hipLaunchKernelGGL(square_tail_kernel<C>, dim3(a.ntail), dim3(C::THREADS), 0,
-                     s, a);
+  hipLaunchKernelGGL((square_tail_kernel<C, MODE>), dim3(a.ntail),
+                     dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
+}
+
+// The step's mode is a template parameter of the kernels, so that the SP2
+// step carries no code of the McWeeny products.
+template <class C>
+hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
+  switch (a.mode) {
+    case 0: return launch_mode<C, 0>(a, grid, s);
+    case 1: return launch_mode<C, 1>(a, grid, s);
+    case 2: return launch_mode<C, 2>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class C>

@@ -1,0 +1,206 @@
+"""GPU parity of McWeeny and McW-ACC (sec. 3) against the FP64 oracle: every
+kernel configuration for one step of the two fused products, full runs in
+every precision, ragged sizes, batches, the mixed norm, bit-exact diagonal
+input and the error paths, through the C ABI."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Status
+from oracle.mcweeny import mcweeny, mw_gamma
+from workloads import config_small, dense_instance, diagonal_instance
+from workloads.banded import banded_instance, to_bsr_blocks
+from tests.gpu_helpers import U32, U64, print_case, square_bound
+
+pytestmark = pytest.mark.gpu
+
+D_TOL = {"fp64": 1e-11, "fp32": 2e-5, "bf16x3": 2e-4}
+
+
+def _configs():
+    try:
+        import paper_1507_02087_amd as sp2
+        return [(c["precision"], c["id"]) for c in sp2.kernel_configs()]
+    except Exception:
+        return [(p, 0) for p in ("fp64", "fp32", "bf16x3")]
+
+
+CONFIGS = _configs()
+
+
+def _mu(inst):
+    return 0.5 * float(inst.lam[inst.n_occ - 1] + inst.lam[inst.n_occ])
+
+
+def _gap(inst):
+    return float(inst.lam[inst.n_occ] - inst.lam[inst.n_occ - 1])
+
+
+def _run(inst, xi=None, **kw):
+    import torch
+    import paper_1507_02087_amd as sp2
+    F = torch.from_numpy(np.ascontiguousarray(inst.F)).to("cuda:0")
+    res = sp2.run_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,
+                        mcweeny=(_mu(inst), xi), **kw)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("prec,cfg", CONFIGS)
+@pytest.mark.parametrize("n", [31, 300])
+@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("acc", [False, True])
+def test_one_step_elementwise(prec, cfg, n, split, acc):
+    """X~_1 of one McWeeny (or McW-ACC) step, element by element, for every
+    configuration: the square's output S, the product X~ S with S as the
+    second operand, and the combination c3 T + c2 S + c1 X~ + c0 I."""
+    inst = dense_instance(n, n // 2, -1.0, 1.3, 0.1, seed=1000 + n)
+    xi = _gap(inst) if acc else None
+    print_case(f"mcweeny one step n={n} prec={prec} cfg={cfg} split={split} acc={acc}")
+    res = _run(inst, xi=xi, precision=prec, max_iter=1, kernel_config=cfg, tail_split=split)
+    ref = mcweeny(inst.F, inst.lambda_min, inst.lambda_max, _mu(inst), xi=xi, max_iter=1)
+    assert res.status_name == "NOT_CONVERGED" and res.n == 1
+    assert ref.status == Status.NOT_CONVERGED
+    a = ref.p[1]
+    b = 0.5 * (1 - a)
+    # |c3|, |c2|, |c1|, |c0| of the expanded step
+    coef = (2 * a ** 3, abs(3 * a * a - 6 * a * a * b), abs(6 * a * b - 6 * a * b * b),
+            abs(3 * b * b - 2 * b ** 3))
+    u = U64 if prec == "fp64" else U32
+    eps_s = square_bound(n, prec) + 4 * u          # S, with X~_0's storage rounding
+    eps_t = (math.sqrt(n) + 1) * eps_s             # T = X~ S carries S's error
+    tol = coef[0] * eps_t + coef[1] * eps_s + 16 * u * sum(coef)
+    D = res.D.cpu().numpy()
+    err = float(np.max(np.abs(D - ref.X)))
+    assert err <= tol, (err, tol)
+    assert np.array_equal(D, D.T)
+    # the first error comes from the square of X~_0
+    assert abs(res.v[0] - ref.v[0]) <= n * square_bound(n, prec) + 1e-6 * ref.v[0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("acc", [False, True])
+def test_full_run(prec, acc):
+    """N = 512: the stop fires with r = log(e_n/4)/log(e_{n-1}) < 1.8, D
+    matches the oracle and the exact D, and the error history follows the
+    oracle's while far above rounding."""
+    inst = config_small()
+    xi = _gap(inst) if acc else None
+    print_case(f"mcweeny full run N=512 prec={prec} acc={acc}")
+    res = _run(inst, xi=xi, precision=prec)
+    ref = mcweeny(inst.F, inst.lambda_min, inst.lambda_max, _mu(inst), xi=xi)
+    assert res.status_name == "OK" and ref.status == Status.OK
+    D = res.D.cpu().numpy()
+    assert np.linalg.norm(D - ref.X) / math.sqrt(inst.n_occ) < D_TOL[prec]
+    D_exact = oracle.density_from_eigenvectors(inst.Q, inst.n_occ)
+    assert np.linalg.norm(D - D_exact) / math.sqrt(inst.n_occ) < D_TOL[prec]
+    k = res.n
+    r = math.log(res.v[k] / 4.0) / math.log(res.v[k - 1])
+    assert r < 1.8 and res.r[k] == pytest.approx(r, rel=1e-12)
+    if prec == "fp64":
+        assert abs(res.n - ref.n) <= 2
+    u_eff = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
+    amp = 1.0
+    for j, (x, y) in enumerate(zip(res.v, ref.v)):
+        if j:
+            amp *= max(1.0, 2 * ref.p[j] ** 3) if j < len(ref.p) else 1.0
+        if y > 1e-3:
+            assert abs(x - y) <= 100 * (j + 1) * u_eff * amp * y + 1e-13, (j, x, y)
+
+
+def test_ragged_padding():
+    """N = 333 padded to the tile: the identity terms stay off the padding."""
+    inst = dense_instance(333, 170, -1.3, 0.9, 0.12, seed=333)
+    for xi in (None, _gap(inst)):
+        res = _run(inst, xi=xi, precision="bf16x3")
+        assert res.status_name == "OK"
+        D = res.D.cpu().numpy()
+        D_exact = oracle.density_from_eigenvectors(inst.Q, inst.n_occ)
+        assert np.linalg.norm(D - D_exact) / math.sqrt(inst.n_occ) < D_TOL["bf16x3"]
+        assert abs(res.t1[res.n] - inst.n_occ) < 1e-3
+
+
+def test_diagonal_bit_exact():
+    """Diagonal F, regular McWeeny in FP64: every product is one scalar
+    product, and the step 3 S - 2 T rounds like the oracle's: bit-exact."""
+    rng = np.random.default_rng(7)
+    d = np.concatenate([rng.uniform(-1, -0.05, 40), rng.uniform(0.05, 1, 24)])
+    inst = diagonal_instance(d, 40, -1.0, 1.0, perm_seed=5)
+    import torch
+    import paper_1507_02087_amd as sp2
+    F = torch.from_numpy(inst.F).cuda()
+    res = sp2.run_dense(F, -1.0, 1.0, 40, mcweeny=(0.0, None), max_iter=6)
+    ref = mcweeny(inst.F, -1.0, 1.0, 0.0, max_iter=6)
+    assert res.status_name == "NOT_CONVERGED" and ref.status == Status.NOT_CONVERGED
+    assert np.array_equal(res.D.cpu().numpy(), ref.X)
+
+
+def test_batch_and_mixed_norm():
+    """A batch (one trivial instance) under McW-ACC with the mixed norm:
+    each instance's m history and result against the oracle."""
+    import torch
+    import paper_1507_02087_amd as sp2
+    insts = [dense_instance(n, n // 2, -1.0, 1.0, g, seed=900 + n)
+             for n, g in ((64, 0.2), (200, 0.05), (333, 0.1))]
+    Fs = [torch.from_numpy(i.F).cuda() for i in insts] + [torch.from_numpy(insts[0].F).cuda()]
+    lo = [i.lambda_min for i in insts] + [-1.0]
+    hi = [i.lambda_max for i in insts] + [1.0]
+    no = [i.n_occ for i in insts] + [64]
+    mus = [_mu(i) for i in insts] + [0.0]
+    xis = [_gap(i) for i in insts] + [0.1]
+    out, _ = sp2.run_batch(Fs, lo, hi, no, precision="fp64", norm="mixed",
+                           mcweeny=(mus, xis))
+    for inst, r in zip(insts, out):
+        ref = mcweeny(inst.F, inst.lambda_min, inst.lambda_max, _mu(inst), xi=_gap(inst),
+                      norm="mixed", mixed_block=32)
+        assert r.status == sp2.OK and ref.status == Status.OK
+        for j, (x, y) in enumerate(zip(r.m, ref.v)):
+            if y > 1e-6:
+                assert x == pytest.approx(y, rel=1e-6), (j, x, y)
+        assert np.linalg.norm(r.D.cpu().numpy() - ref.X) < 1e-11 * math.sqrt(inst.n_occ)
+    assert out[-1].status == sp2.OK and out[-1].n == 0
+    assert torch.equal(out[-1].D.cpu(), torch.eye(64, dtype=torch.float64))
+
+
+def test_argument_errors_and_reinit():
+    import torch
+    import paper_1507_02087_amd as sp2
+    inst = dense_instance(64, 32, -1.0, 1.0, 0.2, seed=2)
+    F = torch.from_numpy(inst.F).cuda()
+    ctx = sp2.Context(0)
+    with pytest.raises(sp2.SP2Error) as e:
+        ctx.set_mcweeny(0.0)
+    assert e.value.status == sp2.BAD_STATE
+    ctx.init_dense(F, -1.0, 1.0, 32)
+    for mu, xi in ((1.5, None), (0.0, 0.0), (0.0, 5.0), (float("nan"), None)):
+        with pytest.raises(sp2.SP2Error) as e:
+            ctx.set_mcweeny(mu, xi)
+        assert e.value.status == sp2.INVALID_ARG
+    ctx.set_homo_lumo(-0.1, -0.1, 0.1, 0.1)
+    with pytest.raises(sp2.SP2Error):       # schedule set: McWeeny refused
+        ctx.set_mcweeny(0.0)
+    ctx.init_dense(F, -1.0, 1.0, 32)
+    ctx.set_mcweeny(0.0)
+    with pytest.raises(sp2.SP2Error):       # McWeeny set: schedule refused
+        ctx.set_homo_lumo(-0.1, -0.1, 0.1, 0.1)
+    assert ctx.run() == sp2.OK
+    n_mw = ctx.get_info()[0]
+    ctx.init_dense(F, -1.0, 1.0, 32)        # back to Alg. 2
+    assert ctx.run() == sp2.OK
+    p = ctx.get_history()["p"]
+    plain = sp2.run_dense(F, -1.0, 1.0, 32)
+    assert p == plain.p and n_mw < plain.n
+    ctx.close()
+    b = banded_instance(n=256, layers=4, seed=3)
+    rp, ci, bl = to_bsr_blocks(b.F, 32)
+    bctx = sp2.BsrContext(0)
+    bctx.init_bsr(256, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                  torch.from_numpy(np.ascontiguousarray(bl)).cuda(), b.lambda_min,
+                  b.lambda_max, b.n_occ)
+    with pytest.raises(sp2.SP2Error) as e:
+        bctx.set_mcweeny(0.0)
+    assert e.value.status == sp2.INVALID_ARG
+    bctx.close()
