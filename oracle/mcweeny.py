@@ -132,7 +132,9 @@ def mcweeny(F: np.ndarray, lambda_min: float, lambda_max: float, mu: float,
             stretch_on = False
             first_test = i + 1
         a = mwa_alpha(beta) if stretch_on else 1.0
-        Xs = _store(a * (X - 0.5 * eye) + 0.5 * eye, working)
+        # the regular expansion applies p_mw to X~ itself; the stretch of
+        # Alg. McW-ACC shifts and scales it first
+        Xs = _store(a * (X - 0.5 * eye) + 0.5 * eye, working) if stretch_on else X
         S = _square(Xs, working)
         S = _store(0.5 * (S + S.T), working)
         T = Xs @ S if working == "fp64" else \
