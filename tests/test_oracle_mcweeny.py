@@ -115,8 +115,9 @@ def test_diagonal_input_scalar_recursion(xi):
     beta = 0.5 * (1 - xi / 2.0) if xi else 0.0
     for k in range(1, res.n + 1):
         a = res.p[k]
-        assert a == (mwa_alpha(beta) if xi and beta >= 0.01 else 1.0)
-        xs = a * (x - 0.5) + 0.5
+        on = bool(xi) and beta >= 0.01
+        assert a == (mwa_alpha(beta) if on else 1.0)
+        xs = a * (x - 0.5) + 0.5 if on else x
         s = xs * xs
         x = 3.0 * s - 2.0 * (xs * s)
         if xi and beta >= 0.01:
