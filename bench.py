@@ -284,7 +284,8 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=0,
                     help="square-kernel configuration id (0 = library choice)")
     ap.add_argument("--no-acc", action="store_true",
-                    help="skip the SP2-ACC comparison run (dense workload)")
+                    help="skip the SP2-ACC, McWeeny and McW-ACC comparison runs "
+                         "(dense workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB twice with torch (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -461,6 +462,31 @@ def main() -> int:
             "status": sp2.STATUS_NAMES[sta], "err_fro_vs_exact_D": erra,
             "speedup_vs_sp2": round(out["value"] / float(np.median(acc_ms)), 2),
         }
+
+    if not args.no_acc:
+        # McWeeny and McW-ACC (sec. 3) on the same input, same precision:
+        # mu at mid-gap, the exact gap as xi; two products per step
+        h = float(inst.lam[inst.n_occ - 1])
+        l = float(inst.lam[inst.n_occ])
+        Qo = inst.Q[:, :inst.n_occ]
+        for key, xi in (("mcweeny", None), ("mcw_acc", l - h)):
+            log(f"[bench] {key} comparison run")
+            ms_l = []
+            for _ in range(max(1, args.steps)):
+                ctx.init_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,
+                               precision=prec)
+                ctx.set_mcweeny(0.5 * (h + l), xi)
+                stm = ctx.run()
+                nm, stepsm, msm = ctx.get_info()
+                ms_l.append(msm)
+            Dm = ctx.get_density(as_fp64=True).cpu().numpy()
+            errm = float(np.linalg.norm(Dm - Qo @ Qo.T))
+            del Dm
+            out[key] = {
+                "time_to_D_ms": round(float(np.median(ms_l)), 3), "n_iter": nm,
+                "steps": stepsm, "matrix_products": 2 * stepsm,
+                "status": sp2.STATUS_NAMES[stm], "err_fro_vs_exact_D": errm,
+            }
 
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample ({args.cpu_squares} squares)")
