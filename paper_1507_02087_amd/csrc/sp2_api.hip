@@ -121,6 +121,10 @@ struct sp2_ctx_s {
   int nf0 = 0;
   void* d_ws = nullptr;
   size_t d_ws_cap = 0;
+  double* d_bpart = nullptr;       // tail bands' partial sums
+  size_t d_bpart_cap = 0;
+  int* d_bcnt = nullptr;           // tail tiles' band counters
+  size_t d_bcnt_cap = 0;
   int32_t* d_ndone = nullptr;
   HostMirror* mirror = nullptr;
   hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -426,7 +430,7 @@ sp2_status setup(sp2_ctx c) {
   for (const HostInst& h : c->hi)
     if (!h.trivial && std::find(cfgs.begin(), cfgs.end(), h.cfg) == cfgs.end())
       cfgs.push_back(h.cfg);
-  size_t ws_elems = 0;
+  size_t ws_elems = 0, max_tail = 0, max_bands = 0;
   for (int cfg : cfgs) {
     const sp2::KernelConfig* kc = sp2::kernel_config(cfg);
     std::vector<int> slots, owner, nk;
@@ -449,6 +453,9 @@ sp2_status setup(sp2_ctx c) {
     // workspace sized for the largest.
     ws_elems = std::max(ws_elems, static_cast<size_t>(g.ntail) * g.split *
                                       kc->bm * kc->bm);
+    max_tail = std::max(max_tail, static_cast<size_t>(g.ntail));
+    max_bands = std::max(max_bands, static_cast<size_t>(g.ntail) *
+                                        (kc->bm / sp2::kMixedBlock));
     c->groups.push_back(g);
     Group& gg = c->groups.back();
     SP2_HIP(c, grow(gg.items, gg.items_cap,
@@ -467,6 +474,15 @@ sp2_status setup(sp2_ctx c) {
     SP2_HIP(c, hipStreamSynchronize(s));
   }
   if (ws_elems) SP2_HIP(c, grow(c->d_ws, c->d_ws_cap, ws_elems * esz, s));
+  if (max_tail) {
+    // the counters start at zero and every tail launch leaves them at zero
+    SP2_HIP(c, grow(c->d_bpart, c->d_bpart_cap,
+                    max_bands * 3 * sizeof(double), s));
+    const size_t old_cap = c->d_bcnt_cap;
+    SP2_HIP(c, grow(c->d_bcnt, c->d_bcnt_cap, max_tail * sizeof(int), s));
+    if (c->d_bcnt_cap != old_cap || old_cap == 0)
+      SP2_HIP(c, hipMemsetAsync(c->d_bcnt, 0, c->d_bcnt_cap, s));
+  }
   SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, count * sizeof(Instance), s));
   SP2_HIP(c, grow(c->d_tiles, c->d_tiles_cap,
                   std::max<size_t>(1, tiles.size()) * sizeof(int2), s));
@@ -524,6 +540,8 @@ sp2_status run_batch(sp2_ctx c) {
   a.tiles = c->d_tiles;
   a.ws = c->d_ws;
   a.part = c->d_part;
+  a.bpart = c->d_bpart;
+  a.bcnt = c->d_bcnt;
   int last = 0;
   const bool any_work = c->bsr || !c->groups.empty();
   for (int i = 1; i <= c->opt.max_iter && any_work; ++i) {
@@ -793,6 +811,8 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_part_f0);
   rel(c->d_f0);
   rel(c->d_ws);
+  rel(c->d_bpart);
+  rel(c->d_bcnt);
   rel(c->d_ndone);
   rel(c->b.mem);
   release_groups(c);

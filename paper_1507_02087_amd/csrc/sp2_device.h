@@ -211,6 +211,8 @@ struct SquareArgs {
   int iter;                   // step i: X~_{i-1} -> X~_i
   int mode;                   // 0 SP2 step; McWeeny: 1 S = X~^2, 2 T = X~ S
   double* part;   // 3 doubles per tile (global slot): ||X - S||_F^2, Tr, sum x^2
+  double* bpart;  // 3 doubles per band of 32 rows of every tail tile
+  int* bcnt;      // per tail tile: bands finished (0 between launches)
 };
 
 // Host-side launchers (implemented in the .hip files).

@@ -1028,36 +1028,41 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
 }
 
 // ============================================================== drivers
-// Accumulator registers are stored to the workspace as [reg][thread] so
-// that every store and load is coalesced across the workgroup.
+// Tile-relative position of accumulator register j of fragment (m, n) held
+// by `lane`: the 16 x 16 FP64 layout, or the 32 x 32 layout of the FP32 and
+// BF16 MFMAs.
+template <class C>
+__device__ __forceinline__ void acc_pos(int m, int n, int j, int lane, int& r,
+                                        int& c) {
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  if (sizeof(typename C::T) == 8) {
+    r = wm + m * 16 + (lane >> 4) + 4 * j;
+    c = wn + n * 16 + (lane & 15);
+  } else {
+    r = wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    c = wn + n * 32 + (lane & 31);
+  }
+}
+
+// A K-range piece of a tail tile is stored row-major (BM x BM), so that the
+// tail reduction can work on bands of rows; a register index is a row
+// segment of 16 or 32 consecutive values across the lanes (coalesced).
 template <class C>
 __device__ __forceinline__ void ws_store(const typename C::Acc& acc,
                                          typename C::T* ws) {
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   constexpr int PER = sizeof(acc.c[0][0]) / sizeof(typename C::T);
-  int k = 0;
 #pragma unroll
   for (int m = 0; m < C::MB; ++m)
 #pragma unroll
     for (int n = 0; n < C::NB; ++n)
 #pragma unroll
-      for (int j = 0; j < PER; ++j, ++k)
-        *grw(ws + static_cast<size_t>(k) * C::THREADS + tid) = acc.c[m][n][j];
-}
-
-template <class C>
-__device__ __forceinline__ void ws_accumulate(typename C::Acc& acc,
-                                              const typename C::T* ws) {
-  const int tid = threadIdx.x;
-  constexpr int PER = sizeof(acc.c[0][0]) / sizeof(typename C::T);
-  int k = 0;
-#pragma unroll
-  for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-    for (int n = 0; n < C::NB; ++n)
-#pragma unroll
-      for (int j = 0; j < PER; ++j, ++k)
-        acc.c[m][n][j] += *gro(ws + static_cast<size_t>(k) * C::THREADS + tid);
+      for (int j = 0; j < PER; ++j) {
+        int r, c;
+        acc_pos<C>(m, n, j, lane, r, c);
+        *grw(ws + static_cast<size_t>(r) * C::BM + c) = acc.c[m][n][j];
+      }
 }
 
 template <class C>
@@ -1179,22 +1184,123 @@ __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   }
 }
 
-// Sums the pieces of tail tile blockIdx.x in piece order, then the epilogue.
+// Tail reduction, one workgroup per band of 32 rows (one block row of the
+// mixed norm) of a tail tile: sums the tile's K pieces in piece order, applies
+// the element epilogue to the band, writes the band and (through LDS, as
+// 32-element row segments) its mirror, and the band's partial sums. The last
+// band of a tile to finish (agent-scope counter) adds the bands' partials in
+// band order into the tile's slot and resets the counter: deterministic.
 template <class C, int MODE>
 __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
-  __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
-  const TailItem t = a.tails[blockIdx.x];
+  using T = typename C::T;
+  constexpr int BM = C::BM, NBAND = BM / kMixedBlock, R = C::THREADS / BM;
+  static_assert(C::THREADS % BM == 0 && kMixedBlock % R == 0 && BM % 64 == 0,
+                "tail band layout");
+  __shared__ T band[kMixedBlock][BM + 1];
+  __shared__ double bred[R][BM / kMixedBlock];
+  __shared__ double sh[C::THREADS / 64][3];
+  __shared__ int is_last;
+  const int ti = blockIdx.x / NBAND, q = blockIdx.x % NBAND;
+  const TailItem t = a.tails[ti];
   const Instance& in = a.inst[t.inst];
   if (in.st->done) return;
-  using T = typename C::T;
   const StepCtx<T> sc = step_ctx<T>(a, in, t.slot);
-  typename C::Acc acc;
-  acc_zero<C>(acc);
-  const T* ws = static_cast<const T*>(a.ws);
-  for (int j = 0; j < a.split; ++j)
-    ws_accumulate<C>(acc, ws + static_cast<size_t>(t.piece0 + j) *
-                                   C::BM * C::BM);
-  Ops<C>::template epi<MODE>(sc, a.part, t.slot, acc, smem);
+  const int I = sc.tile.x, J = sc.tile.y;
+  const bool diag = (I == J);
+  const int ld = sc.ld;
+  const bool split = (sc.Yh != nullptr);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cc = tid % BM, ph = tid / BM;
+  const int r0 = q * kMixedBlock;            // first tile row of the band
+  const int gc = J * BM + cc;
+  const T* ws = static_cast<const T*>(a.ws) +
+                static_cast<size_t>(t.piece0) * BM * BM;
+  Sums sums;
+  double bs = 0.0;
+  for (int jj = 0; jj < kMixedBlock / R; ++jj) {
+    const int rr = ph + R * jj, lr = r0 + rr;
+    const int gr = I * BM + lr;
+    T sv_acc = T(0);
+    for (int p = 0; p < a.split; ++p)
+      sv_acc += *gro(ws + static_cast<size_t>(p) * BM * BM +
+                     static_cast<size_t>(lr) * BM + cc);
+    T xn = T(0);
+    if (!(diag && gr > gc)) {
+      const size_t idx = static_cast<size_t>(gr) * ld + gc;
+      const bool on = (gr == gc);
+      const T sv = (MODE == 2) ? *gro(sc.Sr + idx) : T(0);
+      double d2;
+      xn = epilogue_elem<T, MODE>(sv_acc, *gro(sc.X + idx), sv, sc.k, sc.tau,
+                                  on ? 1.0 : 2.0, on && gr < sc.n, sums, d2);
+      *grw(sc.Y + idx) = xn;
+      if (split) store_split(sc.Yh, sc.Yl, idx, xn);
+      bs += block_share(gr, gc, d2);
+    }
+    band[rr][cc] = xn;
+  }
+  if (MODE != 2 && sc.blk) {
+    bs = half_wave_sum(bs);
+    if ((lane & 31) == 0) bred[ph][cc / kMixedBlock] = bs;
+  }
+  __syncthreads();
+  if (MODE != 2 && sc.blk && tid < BM / kMixedBlock) {
+    double tb = 0.0;
+    for (int p = 0; p < R; ++p) tb += bred[p][tid];
+    const int grb = (I * BM + r0) / kMixedBlock, gcb = J * BM / kMixedBlock + tid;
+    if (grb <= gcb) blk_write(sc.blk, sc.nbk, grb, gcb, tb);
+  }
+  // mirror: element (c, rr) of the transpose, 32 consecutive rows of the
+  // band per column
+  for (int e = tid; e < kMixedBlock * BM; e += C::THREADS) {
+    const int c = e / kMixedBlock, rr = e % kMixedBlock;
+    const int gr = I * BM + r0 + rr, gcc = J * BM + c;
+    if (diag && gr >= gcc) continue;
+    const size_t idt = static_cast<size_t>(gcc) * ld + gr;
+    const T xn = band[rr][c];
+    *grw(sc.Y + idt) = xn;
+    if (split) store_split(sc.Yh, sc.Yl, idt, xn);
+  }
+  // partial sums of the band, then of the tile
+  sums.v = wave_sum(sums.v);
+  sums.t1 = wave_sum(sums.t1);
+  sums.t2 = wave_sum(sums.t2);
+  if (lane == 0) {
+    sh[wave][0] = sums.v;
+    sh[wave][1] = sums.t1;
+    sh[wave][2] = sums.t2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v = sh[0][0], t1 = sh[0][1], t2 = sh[0][2];
+    for (int w = 1; w < C::THREADS / 64; ++w) {
+      v += sh[w][0];
+      t1 += sh[w][1];
+      t2 += sh[w][2];
+    }
+    double* bp = a.bpart + 3 * (static_cast<size_t>(ti) * NBAND + q);
+    bp[0] = v;
+    bp[1] = t1;
+    bp[2] = t2;
+    const int before = __hip_atomic_fetch_add(a.bcnt + ti, 1, __ATOMIC_ACQ_REL,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (before == NBAND - 1);
+  }
+  __syncthreads();
+  if (tid == 0 && is_last) {
+    double v = 0.0, t1 = 0.0, t2 = 0.0;
+    const double* bp = a.bpart + 3 * static_cast<size_t>(ti) * NBAND;
+    for (int b = 0; b < NBAND; ++b) {
+      v += bp[3 * b + 0];
+      t1 += bp[3 * b + 1];
+      t2 += bp[3 * b + 2];
+    }
+    if (MODE != 2) a.part[3 * t.slot + 0] = v;
+    if (MODE != 1) {
+      a.part[3 * t.slot + 1] = t1;
+      a.part[3 * t.slot + 2] = t2;
+    }
+    a.bcnt[ti] = 0;
+  }
 }
 
 // Kernel configurations: macro tile, waves (M x N), K slice.
@@ -1222,8 +1328,9 @@ hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
                      s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ntail == 0) return e;
-  hipLaunchKernelGGL((square_tail_kernel<C, MODE>), dim3(a.ntail),
-                     dim3(C::THREADS), 0, s, a);
+  hipLaunchKernelGGL((square_tail_kernel<C, MODE>),
+                     dim3(a.ntail * (C::BM / kMixedBlock)), dim3(C::THREADS), 0,
+                     s, a);
   return hipGetLastError();
 }
 
