@@ -853,84 +853,6 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   }
 }
 
-// "Q" family: pre-split operands like "P", one K slice of register
-// prefetch (for one wave per SIMD, where the accumulators take the AGPRs).
-template <int BM_, int WM_, int WN_, int BK_>
-struct CfgB3Q : CfgB3S<BM_, WM_, WN_, BK_> {};
-
-template <class C>
-__device__ __forceinline__ void mainloop_b3q(const StepCtx<float>& sc,
-                                             const WorkItem& w,
-                                             typename C::Acc& acc,
-                                             char* smem) {
-  __bf16* lds = reinterpret_cast<__bf16*>(smem);
-  auto arr = [&](int b, int a) { return lds + (b * 4 + a) * C::ARR; };
-  const int2 tt = sc.tile;
-  const int ld = sc.ld;
-  const size_t ao = static_cast<size_t>(tt.x * C::BM) * ld;
-  const size_t bo = static_cast<size_t>(tt.y * C::BM) * ld;
-  const __bf16 *Ah = sc.Xh + ao, *Al = sc.Xl + ao;
-  const __bf16 *Bh = sc.Bh + bo, *Bl = sc.Bl + bo;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
-  const int r = lane & 31, h = lane >> 5;
-  using St = SplitStage<C>;
-  St st;
-  auto sstore = [&](int b) {
-#pragma unroll
-    for (int q = 0; q < St::NC; ++q) {
-      const int o = swz_off<C::BK>(St::row(tid, q), St::col(tid, q));
-      *reinterpret_cast<bf16x8*>(arr(b, 0) + o) = st.ah[q];
-      *reinterpret_cast<bf16x8*>(arr(b, 1) + o) = st.al[q];
-      *reinterpret_cast<bf16x8*>(arr(b, 2) + o) = st.bh[q];
-      *reinterpret_cast<bf16x8*>(arr(b, 3) + o) = st.bl[q];
-    }
-  };
-  auto compute = [&](int b) {
-#pragma unroll
-    for (int s8 = 0; s8 < C::KH; s8 += 8) {
-      bf16x8 bh[C::NB], bl[C::NB];
-#pragma unroll
-      for (int n = 0; n < C::NB; ++n) {
-        const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
-        bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
-        bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
-      }
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) {
-        const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah, bh[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah, bl[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              al, bh[n], acc.c[m][n], 0, 0, 0);
-      }
-    }
-  };
-  acc_zero<C>(acc);
-  const int k0 = w.k0, k1 = w.k1;
-  st.load(Ah, Al, Bh, Bl, ld, k0 * C::BK, tid);
-  sstore(0);
-  if (k0 + 1 < k1) st.load(Ah, Al, Bh, Bl, ld, (k0 + 1) * C::BK, tid);
-  __syncthreads();
-  for (int kt = k0; kt < k1; ++kt) {
-    const int b = (kt - k0) & 1;
-    compute(b);
-    if (kt + 1 < k1) sstore(b ^ 1);
-    if (kt + 2 < k1) st.load(Ah, Al, Bh, Bl, ld, (kt + 2) * C::BK, tid);
-    __syncthreads();
-  }
-}
-
 // Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
 // (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
 // The tile is processed one band of TM rows at a time (the rows of one row
@@ -1149,22 +1071,6 @@ struct Ops<CfgB3P<A, B, Cc, D>> {
   }
 };
 
-template <int A, int B, int Cc, int D>
-struct Ops<CfgB3Q<A, B, Cc, D>> {
-  using C = CfgB3Q<A, B, Cc, D>;
-  using T = typename C::T;
-  static constexpr int kSmem = C::SMEM;
-  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc, char* smem) {
-    mainloop_b3q<C>(sc, w, acc, smem);
-  }
-  template <int MODE>
-  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
-  }
-};
-
 template <class C, int MODE>
 __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
@@ -1319,8 +1225,6 @@ using B3S_128_2x2 = CfgB3S<128, 2, 2, 32>;
 using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
 using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
 using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
-using B3Q_256_2x2 = CfgB3Q<256, 2, 2, 32>;
-using B3Q_256_2x2_16 = CfgB3Q<256, 2, 2, 16>;
 
 template <class C, int MODE>
 hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
@@ -1364,8 +1268,7 @@ const KernelConfig kConfigs[] = {
     SP2_DESCRIBE(B3_256_2x4, 2, 1),  SP2_DESCRIBE(B3S_256_2x4, 2, 1),
     SP2_DESCRIBE(B3S_256_2x4_16, 2, 1), SP2_DESCRIBE(B3S_128_2x2, 2, 2),
     SP2_DESCRIBE(B3P_256_2x4, 2, 1), SP2_DESCRIBE(B3P_256_2x4_32, 2, 1),
-    SP2_DESCRIBE(B3P_128_2x2, 2, 2), SP2_DESCRIBE(B3Q_256_2x2, 2, 1),
-    SP2_DESCRIBE(B3Q_256_2x2_16, 2, 1),
+    SP2_DESCRIBE(B3P_128_2x2, 2, 2),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -1394,8 +1297,6 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 12: return launch_cfg<B3P_256_2x4>(a, grid, s);
     case 13: return launch_cfg<B3P_256_2x4_32>(a, grid, s);
     case 14: return launch_cfg<B3P_128_2x2>(a, grid, s);
-    case 15: return launch_cfg<B3Q_256_2x2>(a, grid, s);
-    case 16: return launch_cfg<B3Q_256_2x2_16>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
