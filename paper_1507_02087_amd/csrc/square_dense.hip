@@ -1121,15 +1121,37 @@ __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   const int gc = J * BM + cc;
   const T* ws = static_cast<const T*>(a.ws) +
                 static_cast<size_t>(t.piece0) * BM * BM;
+  // Sum of the pieces for the thread's rows ph + R jj of the band, in piece
+  // order; four pieces of all rows are loaded at a time so that many
+  // independent loads are in flight.
+  constexpr int NR = kMixedBlock / R;
+  T rows[NR];
+#pragma unroll
+  for (int jj = 0; jj < NR; ++jj) rows[jj] = T(0);
+  const T* src = ws + static_cast<size_t>(r0 + ph) * BM + cc;
+  for (int p0 = 0; p0 < a.split; p0 += 4) {
+    T v[4][NR];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int jj = 0; jj < NR; ++jj)
+        v[p][jj] = (p0 + p < a.split)
+                       ? *gro(src + static_cast<size_t>(p0 + p) * BM * BM +
+                              static_cast<size_t>(R * jj) * BM)
+                       : T(0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int jj = 0; jj < NR; ++jj)
+        if (p0 + p < a.split) rows[jj] += v[p][jj];
+  }
   Sums sums;
   double bs = 0.0;
-  for (int jj = 0; jj < kMixedBlock / R; ++jj) {
+#pragma unroll
+  for (int jj = 0; jj < NR; ++jj) {
     const int rr = ph + R * jj, lr = r0 + rr;
     const int gr = I * BM + lr;
-    T sv_acc = T(0);
-    for (int p = 0; p < a.split; ++p)
-      sv_acc += *gro(ws + static_cast<size_t>(p) * BM * BM +
-                     static_cast<size_t>(lr) * BM + cc);
+    const T sv_acc = rows[jj];
     T xn = T(0);
     if (!(diag && gr > gc)) {
       const size_t idx = static_cast<size_t>(gr) * ld + gc;
