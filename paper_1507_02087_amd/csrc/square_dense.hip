@@ -853,104 +853,6 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   }
 }
 
-// "D" family: pre-split operands like "P", staged by direct global-to-LDS
-// loads (global_load_lds_dwordx4): each instruction moves 64 x 16 bytes into
-// 1 KiB of LDS at consecutive 16-byte slots, so every lane fetches the
-// global chunk that belongs to its slot under the XOR swizzle (the swizzle is
-// its own inverse). No staging registers; the next slice's loads are issued
-// before the current slice's MFMAs and waited for before the barrier.
-template <int BM_, int WM_, int WN_, int BK_>
-struct CfgB3D : CfgB3S<BM_, WM_, WN_, BK_> {};
-
-template <class C>
-__device__ __forceinline__ void mainloop_b3d(const StepCtx<float>& sc,
-                                             const WorkItem& w,
-                                             typename C::Acc& acc,
-                                             char* smem) {
-  __bf16* lds = reinterpret_cast<__bf16*>(smem);
-  auto arr = [&](int b, int a) { return lds + (b * 4 + a) * C::ARR; };
-  const int2 tt = sc.tile;
-  const int ld = sc.ld;
-  const size_t ao = static_cast<size_t>(tt.x * C::BM) * ld;
-  const size_t bo = static_cast<size_t>(tt.y * C::BM) * ld;
-  const __bf16* src[4] = {sc.Xh + ao, sc.Xl + ao, sc.Bh + bo, sc.Bl + bo};
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
-  const int r = lane & 31, h = lane >> 5;
-  constexpr int CPR = C::BK / 8;                    // 16-byte chunks per row
-  constexpr int SHIFT = C::BK == 16 ? 3 : (C::BK == 32 ? 2 : 1);
-  constexpr int PER_ARR = C::BM * CPR / 64;         // 1 KiB loads per array
-  constexpr int NLOAD = 4 * PER_ARR;                // per slice and workgroup
-  constexpr int NWAVE = C::THREADS / 64;
-  static_assert(NLOAD % NWAVE == 0, "loads per wave");
-  // wave-invariant part of each of this wave's loads: array, LDS slot of
-  // the lane, global element offset within the panel (without k0)
-  auto issue = [&](int kt, int b) {
-#pragma unroll
-    for (int i = 0; i < NLOAD / NWAVE; ++i) {
-      const int g = wave * (NLOAD / NWAVE) + i;
-      const int a = g / PER_ARR, sub = g % PER_ARR;
-      const int slot = sub * 64 + lane;             // 16-byte slot in the array
-      const int row = slot / CPR, chp = slot % CPR;
-      const int ch = chp ^ ((row >> SHIFT) & (CPR - 1));
-      const __bf16* gp = src[a] + static_cast<size_t>(row) * ld + kt * C::BK +
-                         ch * 8;
-      __bf16* lp = arr(b, a) + sub * 64 * 8;        // wave-uniform 1 KiB
-      __builtin_amdgcn_global_load_lds(
-          (const __attribute__((address_space(1))) void*)gp,
-          (__attribute__((address_space(3))) void*)lp, 16, 0, 0);
-    }
-  };
-  auto compute = [&](int b) {
-#pragma unroll
-    for (int s8 = 0; s8 < C::KH; s8 += 8) {
-      bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) {
-        const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
-        ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
-        al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
-      }
-#pragma unroll
-      for (int n = 0; n < C::NB; ++n) {
-        const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
-        bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
-        bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
-      }
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m], bh[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m], bl[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              al[m], bh[n], acc.c[m][n], 0, 0, 0);
-    }
-  };
-  acc_zero<C>(acc);
-  const int k0 = w.k0, k1 = w.k1;
-  issue(k0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int kt = k0; kt < k1; ++kt) {
-    const int b = (kt - k0) & 1;
-    if (kt + 1 < k1) issue(kt + 1, b ^ 1);
-    compute(b);
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed in LDS
-    __syncthreads();
-  }
-}
-
 // Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
 // (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
 // The tile is processed one band of TM rows at a time (the rows of one row
@@ -1169,22 +1071,6 @@ struct Ops<CfgB3P<A, B, Cc, D>> {
   }
 };
 
-template <int A, int B, int Cc, int D>
-struct Ops<CfgB3D<A, B, Cc, D>> {
-  using C = CfgB3D<A, B, Cc, D>;
-  using T = typename C::T;
-  static constexpr int kSmem = C::SMEM;
-  __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc, char* smem) {
-    mainloop_b3d<C>(sc, w, acc, smem);
-  }
-  template <int MODE>
-  __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
-  }
-};
-
 template <class C, int MODE>
 __global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
@@ -1361,8 +1247,6 @@ using B3S_128_2x2 = CfgB3S<128, 2, 2, 32>;
 using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
 using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
 using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
-using B3D_256_2x4_32 = CfgB3D<256, 2, 4, 32>;
-using B3D_256_2x4 = CfgB3D<256, 2, 4, 16>;
 
 template <class C, int MODE>
 hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
@@ -1406,8 +1290,7 @@ const KernelConfig kConfigs[] = {
     SP2_DESCRIBE(B3_256_2x4, 2, 1),  SP2_DESCRIBE(B3S_256_2x4, 2, 1),
     SP2_DESCRIBE(B3S_256_2x4_16, 2, 1), SP2_DESCRIBE(B3S_128_2x2, 2, 2),
     SP2_DESCRIBE(B3P_256_2x4, 2, 1), SP2_DESCRIBE(B3P_256_2x4_32, 2, 1),
-    SP2_DESCRIBE(B3P_128_2x2, 2, 2), SP2_DESCRIBE(B3D_256_2x4_32, 2, 1),
-    SP2_DESCRIBE(B3D_256_2x4, 2, 1),
+    SP2_DESCRIBE(B3P_128_2x2, 2, 2),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -1436,8 +1319,6 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 12: return launch_cfg<B3P_256_2x4>(a, grid, s);
     case 13: return launch_cfg<B3P_256_2x4_32>(a, grid, s);
     case 14: return launch_cfg<B3P_128_2x2>(a, grid, s);
-    case 15: return launch_cfg<B3D_256_2x4_32>(a, grid, s);
-    case 16: return launch_cfg<B3D_256_2x4>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
