@@ -83,7 +83,7 @@ typedef enum {
 /* Norm of X~_k - X~_k^2 that the stop test uses (sec. 2). */
 typedef enum {
   SP2_NORM_FROBENIUS = 0,  /* v_k = ||.||_F (default) */
-  SP2_NORM_MIXED = 1       /* m_k = spectral norm of the matrix of Frobenius
+  SP2_NORM_MIXED = 1,      /* m_k = spectral norm of the matrix of Frobenius
                               norms of the 32 x 32 blocks (the block size of
                               sec. 6); spectral <= mixed <= Frobenius, and for
                               large n it stays below 1 where the Frobenius
@@ -93,6 +93,21 @@ typedef enum {
                               reorthogonalisation, at most 64 steps, until
                               the top Ritz value changes by < 1e-12
                               relative) */
+  SP2_NORM_SPECTRAL = 2    /* e_k = ||X~_k - X~_k^2||_2, the error of Alg. 2
+                              as printed: dense and batched runs only. Found
+                              by Lanczos on E = X~_k - X~_k^2 applied as
+                              X~_k q - X~_k (X~_k q) to the stored iterate in
+                              FP64 arithmetic (E is never formed): full
+                              reorthogonalisation, at most 64 steps (two
+                              products with X~_k each), until the estimate
+                              max(|top|, |bottom| Ritz value) changes by
+                              < 1e-12 relative. The Ritz values lie inside
+                              E's spectrum, so the estimate never exceeds the
+                              norm; where E's top eigenvalues cluster (the
+                              first steps) it may stay below it by ~1e-4
+                              relative. One cooperative launch per step
+                              (every workgroup resident at once) runs the
+                              Lanczos processes of all instances */
 } sp2_norm;
 
 /* Block edge of SP2_NORM_MIXED. */
@@ -181,6 +196,15 @@ sp2_status sp2_get_info(sp2_ctx ctx, int32_t* n_iter, int32_t* n_squares,
  * SP2_NORM_MIXED, SP2_INVALID_ARG. */
 sp2_status sp2_get_mixed_history(sp2_ctx ctx, int32_t index, int32_t cap,
                                  int32_t* len, double* m);
+
+/* History of the error the stop test read, for a run with the mixed or the
+ * spectral norm: e[k] = ||X~_k - X~_k^2|| in that norm for
+ * k = 0..n_squares-1 (sec. 2; Alg. 2 for the spectral norm), same
+ * conventions as sp2_get_mixed_history; the Frobenius norms stay available
+ * through sp2_get_history. Errors: SP2_BAD_STATE before a run or after a
+ * Frobenius-norm run, SP2_INVALID_ARG. */
+sp2_status sp2_get_norm_history(sp2_ctx ctx, int32_t index, int32_t cap,
+                                int32_t* len, double* e);
 
 /* Per-step history of the last run, host arrays of capacity `cap`:
  * v[k] = ||X~_k - X~_k^2||_F for k = 0..n_squares-1; t1[k] = Tr X~_k and
@@ -352,12 +376,15 @@ sp2_status sp2_set_homo_lumo(sp2_ctx ctx, int32_t count,
  * mu - lambda_min); each step X_i = 3 X_s^2 - 2 X_s^3 with
  * X_s = alpha_i (X~_{i-1} - I/2) + I/2, truncation as in SP2, and the stop
  * at the first step k with log(e_k / 4) / log(e_{k-1}) < 1.8 (e = the
- * Frobenius or mixed norm of X~_k - X~_k^2, evaluated when 0 < e_{k-1} < 1).
+ * Frobenius, mixed or spectral norm of X~_k - X~_k^2, evaluated when
+ * 0 < e_{k-1} < 1).
  * Regular McWeeny: alpha = 1. McW-ACC with gap estimate xi:
  * beta_0 = (1 - xi / gamma) / 2, alpha_i = 3 / sqrt(12 beta^2 - 18 beta + 9),
  * beta_i = p_mw(alpha_i (beta_{i-1} - 1/2) + 1/2); the stretch is switched
  * off (alpha = 1) once beta < 0.01 and the stop is tested from the step
- * after (the Frobenius estimate can stop too early while it is on).
+ * after (the Frobenius estimate can stop too early while it is on); with
+ * SP2_NORM_SPECTRAL the stretch stays on and the stop is tested from step 1
+ * as printed.
  * Each step computes two products, S = X~^2 (which also gives e_{i-1}) and
  * X~ S, and forms the new iterate from them in the second one's epilogue.
  * --------------------------------------------------------------------- */

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP_ERROR",
                 4: "NOT_CONVERGED", 5: "DIVERGED", 6: "BAD_STATE"}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 BRANCHES = {"nearest": 0, "literal": 1}
-NORMS = {"fro": 0, "mixed": 1}
+NORMS = {"fro": 0, "mixed": 1, "spectral": 2}
 MIXED_BLOCK = 32
 MAX_ITER_LIMIT = 200
 
@@ -46,6 +46,8 @@ SIGNATURES = {
                                         _c.c_void_p]),
     "sp2_get_mixed_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
                                          _c.POINTER(_c.c_int32), _c.c_void_p]),
+    "sp2_get_norm_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
+                                        _c.POINTER(_c.c_int32), _c.c_void_p]),
     "sp2_init_bsr": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int64,
                                 _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
                                 _c.c_double, _c.c_int64, _c.c_void_p]),
@@ -141,7 +143,7 @@ class Result:
     t2: list = field(default_factory=list)
     p: list = field(default_factory=list)
     r: list = field(default_factory=list)
-    m: list = field(default_factory=list)    # mixed-norm history (norm="mixed")
+    m: list = field(default_factory=list)    # history of the mixed or spectral norm
 
     @property
     def status_name(self) -> str:
@@ -306,13 +308,19 @@ class Context:
 
     def get_mixed_history(self, index: int = 0):
         """m[k] = mixed norm of X~_k - X~_k^2 of the last run (norm="mixed")."""
+        return self._norm_history("sp2_get_mixed_history", index)
+
+    def get_norm_history(self, index: int = 0):
+        """e[k] = ||X~_k - X~_k^2|| in the norm the stop read (norm="mixed"
+        or "spectral") of the last run."""
+        return self._norm_history("sp2_get_norm_history", index)
+
+    def _norm_history(self, fn: str, index: int):
         import numpy as np
         ln = ctypes.c_int32()
         m = np.full(MAX_ITER_LIMIT + 1, np.nan)
-        self._check(self._lib.sp2_get_mixed_history(self._h, index, m.size,
-                                                    ctypes.byref(ln),
-                                                    ctypes.c_void_p(m.ctypes.data)),
-                    "sp2_get_mixed_history")
+        self._check(getattr(self._lib, fn)(self._h, index, m.size, ctypes.byref(ln),
+                                           ctypes.c_void_p(m.ctypes.data)), fn)
         return m[:ln.value].tolist()
 
     def get_config(self, index: int = 0):
@@ -504,7 +512,7 @@ def run_batch(Fs, lambda_min, lambda_max, n_occ, ctx: BatchContext | None = None
         out = []
         for b in range(len(Fs)):
             D, st, n, sq = ctx.batch_get(b, as_fp64=as_fp64)
-            m = ctx.get_mixed_history(b) if opts.get("norm") == "mixed" else []
+            m = ctx.get_norm_history(b) if opts.get("norm", "fro") != "fro" else []
             out.append(Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, m=m,
                               **ctx.batch_history(b)))
         return out, ms
@@ -537,7 +545,7 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
         D = ctx.get_density(as_fp64=as_fp64)
         n, sq, ms = ctx.get_info()
         h = ctx.get_history()
-        m = ctx.get_mixed_history() if norm == "mixed" else []
+        m = ctx.get_norm_history() if norm != "fro" else []
         return Result(D=D, status=st, n=n, n_squares=sq, run_ms=ms, m=m, **h)
     finally:
         if own:

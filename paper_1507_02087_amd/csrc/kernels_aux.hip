@@ -3,6 +3,7 @@
 #include <math.h>
 
 #include "sp2_device.h"
+#include "tridiag.h"
 
 namespace sp2 {
 
@@ -53,9 +54,8 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c,
 }
 
 // Clears the states of `count` instances and the batch's done counter.
-__global__ __launch_bounds__(kThreads) void state_reset_kernel(DevState* st,
-                                                               int count,
-                                                               int32_t* ndone) {
+__global__ __launch_bounds__(kThreads) void state_reset_kernel(
+    DevState* st, int count, int32_t* ndone, int32_t* zero, int nzero) {
   DevState* me = st + blockIdx.x;
   int32_t* w = reinterpret_cast<int32_t*>(me);
   const int words = static_cast<int>(sizeof(DevState) / sizeof(int32_t));
@@ -66,6 +66,8 @@ __global__ __launch_bounds__(kThreads) void state_reset_kernel(DevState* st,
     me->alpha[0] = 1.0;
     if (blockIdx.x == 0) *ndone = 0;
   }
+  if (blockIdx.x == 0 && zero)
+    for (int i = threadIdx.x; i < nzero; i += kThreads) zero[i] = 0;
 }
 
 // X_0 = (lambda_max I - F) / (lambda_max - lambda_min) in FP64 (Alg. 2),
@@ -139,53 +141,6 @@ __device__ __forceinline__ double block_sum_all(double x, double* red) {
 
 constexpr int kMaxBlockRows = 2048;   // n / 32 for n <= 65536
 
-// Number of eigenvalues of the symmetric tridiagonal matrix (diagonal a,
-// off-diagonal b, order m) below x: Sturm count of the LDL^T pivots.
-__device__ __forceinline__ int sturm_below(const double* a, const double* b,
-                                           int m, double x) {
-  int cnt = 0;
-  double d = 1.0;
-  for (int i = 0; i < m; ++i) {
-    const double bb = (i > 0) ? b[i - 1] * b[i - 1] : 0.0;
-    d = (a[i] - x) - ((i > 0) ? bb / d : 0.0);
-    if (d == 0.0) d = -1e-300;
-    if (d < 0.0) ++cnt;
-  }
-  return cnt;
-}
-
-// Largest eigenvalue of the tridiagonal (a, b) of order m by multisection:
-// every thread counts at one point of the current bracket, and the bracket
-// shrinks to the two points around the top eigenvalue; five rounds of 256
-// points narrow a Gershgorin bracket by 256^5.
-__device__ double tridiag_top(const double* a, const double* b, int m,
-                              int* hits) {
-  double lo = a[0], hi = a[0];
-  for (int i = 0; i < m; ++i) {
-    const double r = ((i > 0) ? fabs(b[i - 1]) : 0.0) +
-                     ((i + 1 < m) ? fabs(b[i]) : 0.0);
-    lo = fmin(lo, a[i] - r);
-    hi = fmax(hi, a[i] + r);
-  }
-  for (int round = 0; round < 5; ++round) {
-    const double h = (hi - lo) / kThreads;
-    const double x = lo + h * (threadIdx.x + 1);
-    // hits[t] = 1 when every eigenvalue lies below the point x_t
-    __syncthreads();
-    hits[threadIdx.x] = (sturm_below(a, b, m, x) == m) ? 1 : 0;
-    __syncthreads();
-    int first = kThreads - 1;   // smallest t with all eigenvalues below x_t
-    for (int t = 0; t < kThreads; ++t)
-      if (hits[t]) {
-        first = t;
-        break;
-      }
-    hi = lo + h * (first + 1);
-    lo = lo + h * first;
-  }
-  return 0.5 * (lo + hi);
-}
-
 constexpr int kLanczos = kLanczosMax;  // Krylov dimension cap
 constexpr double kLanczosTol = 1e-12; // relative change of the top Ritz value
 
@@ -252,7 +207,7 @@ __device__ double mixed_norm(const Instance& in, int iter, double* w,
     const double beta = sqrt(ww);
     m = j + 1;
     const double prev = theta;
-    theta = tridiag_top(ta, tb, m, hits);
+    theta = tridiag_eig(ta, tb, m, m, hits);   // the top eigenvalue
     // an invariant subspace (beta ~ 0), convergence, or the last step
     if (!(beta > 1e-14 * fabs(theta)) || !isfinite(beta) ||
         (j > 0 && fabs(theta - prev) <= kLanczosTol * fabs(theta)) ||
@@ -333,10 +288,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     const int k = iter - 1;
     const double vk = sqrt(a);
     st->v[k] = vk;
-    st->m[k] = mk;
+    if (prm.norm == 1) st->m[k] = mk;   // the spectral kernel wrote m[k]
     st->squares = iter;
-    // the error the stop test reads: Frobenius, or mixed (sec. 2)
-    const double* e = (prm.norm == 1) ? st->m : st->v;
+    // the error the stop test reads: Frobenius, mixed or spectral (sec. 2)
+    const double* e = (prm.norm != 0) ? st->m : st->v;
     const double ek = e[k];
     double r = NAN;
     if (mw) {
@@ -389,18 +344,20 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   // traces of X~_iter (Alg. 2 branch). Past the schedule's end one more
   // square is needed for v_{n_max}; the iterate it yields is not used.
   // McWeeny: the stretch of McW-ACC from beta, switched off (and the stop
-  // enabled from the step after) once beta < 0.01; the regular expansion
-  // tests the stop from step 1.
+  // enabled from the step after) once beta < 0.01 with the Frobenius or the
+  // mixed norm; the regular expansion, and McW-ACC with the spectral norm,
+  // test the stop from step 1.
   int pn;
   double an = 1.0;
   if (mw) {
     if (iter == 0) {
       st->mw_beta = prm.mw_beta0;
       st->mw_stretch = prm.mw_acc;
-      st->mw_first = prm.mw_acc ? 0 : 1;
+      st->mw_first = (prm.mw_acc && prm.norm != 2) ? 0 : 1;
     }
     const int i = iter + 1;
-    if (st->mw_stretch && st->mw_beta < kMwDelta) {
+    // with the spectral norm the stretch stays on and every step is tested
+    if (st->mw_stretch && prm.norm != 2 && st->mw_beta < kMwDelta) {
       st->mw_stretch = 0;
       st->mw_first = i + 1;
     }
@@ -450,9 +407,9 @@ int grid_for(int64_t total) {
 }  // namespace
 
 hipError_t launch_state_reset(DevState* st, int count, int32_t* ndone,
-                              hipStream_t s) {
+                              int32_t* zero, int nzero, hipStream_t s) {
   hipLaunchKernelGGL(state_reset_kernel, dim3(count), dim3(kThreads), 0, s, st,
-                     count, ndone);
+                     count, ndone, zero, nzero);
   return hipGetLastError();
 }
 

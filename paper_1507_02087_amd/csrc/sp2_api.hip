@@ -108,6 +108,16 @@ struct sp2_ctx_s {
   size_t d_blk_cap = 0;
   double* d_lz = nullptr;          // Lanczos bases of the mixed norm
   size_t d_lz_cap = 0;
+  // spectral norm: Lanczos scratch of every instance, the chunk table of the
+  // spectral launch, and one counter of final estimates per step
+  double* d_spec = nullptr;
+  size_t d_spec_cap = 0;
+  int2* d_spec_chunks = nullptr;
+  size_t d_spec_chunks_cap = 0;
+  int32_t* d_spec_ctl = nullptr;
+  size_t d_spec_ctl_cap = 0;
+  int spec_nchunks = 0;
+  int spec_grid = 0;
   DevState* d_st = nullptr;
   size_t d_st_cap = 0;
   int2* d_tiles = nullptr;
@@ -300,7 +310,8 @@ sp2_status validate_options(sp2_ctx c, sp2_options& opt) {
   }
   if (opt.tail_split < 0 || opt.tail_split > 64)
     return fail(c, SP2_INVALID_ARG, "tail_split outside [0, 64]", hipSuccess);
-  if (opt.norm != SP2_NORM_FROBENIUS && opt.norm != SP2_NORM_MIXED)
+  if (opt.norm != SP2_NORM_FROBENIUS && opt.norm != SP2_NORM_MIXED &&
+      opt.norm != SP2_NORM_SPECTRAL)
     return fail(c, SP2_INVALID_ARG, "unknown norm", hipSuccess);
   if (opt.reserved != 0)
     return fail(c, SP2_INVALID_ARG, "reserved option field must be 0",
@@ -381,6 +392,40 @@ sp2_status setup(sp2_ctx c) {
     SP2_HIP(c, grow(c->d_lz, c->d_lz_cap, lz_elems * sizeof(double), s));
   }
 
+  // spectral norm: Lanczos scratch per instance and the chunk table (rows
+  // of the non-trivial instances in chunks of kSpecRows)
+  const bool spectral = (c->opt.norm == SP2_NORM_SPECTRAL);
+  std::vector<size_t> sp_off(count, 0);
+  std::vector<int2> chunks;
+  std::vector<int> sp_ch0(count, 0), sp_nch(count, 0);
+  if (spectral) {
+    size_t sp_elems = 0;
+    for (int b = 0; b < count; ++b) {
+      const HostInst& h = c->hi[b];
+      sp_off[b] = sp_elems;
+      sp_elems += sp2::spec_doubles(static_cast<int>(h.n));
+      if (h.trivial) continue;
+      sp_ch0[b] = static_cast<int>(chunks.size());
+      for (int r = 0; r < h.n; r += sp2::kSpecRows) chunks.push_back(int2{b, r});
+      sp_nch[b] = static_cast<int>(chunks.size()) - sp_ch0[b];
+    }
+    SP2_HIP(c, grow(c->d_spec, c->d_spec_cap, sp_elems * sizeof(double), s));
+    SP2_HIP(c, grow(c->d_spec_chunks, c->d_spec_chunks_cap,
+                    std::max<size_t>(1, chunks.size()) * sizeof(int2), s));
+    SP2_HIP(c, grow(c->d_spec_ctl, c->d_spec_ctl_cap,
+                    (sp2::kMaxIter + 2) * sizeof(int32_t), s));
+    if (!chunks.empty())
+      SP2_HIP(c, hipMemcpyAsync(c->d_spec_chunks, chunks.data(),
+                                chunks.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s));
+    const int gmax = sp2::spectral_max_grid(c->fp64_store, c->num_cus);
+    if (gmax < 1)
+      return fail(c, SP2_HIP_ERROR, "spectral kernel: no co-resident grid",
+                  hipGetLastError());
+    c->spec_grid = std::min<int>(gmax, static_cast<int>(chunks.size()));
+  }
+  c->spec_nchunks = static_cast<int>(chunks.size());
+
   // instance table, tiles and affine-start blocks
   SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
   std::vector<int2> tiles;
@@ -421,6 +466,9 @@ sp2_status setup(sp2_ctx c) {
     in.nbk = static_cast<int>(h.np / sp2::kMixedBlock);
     in.blk = mixed ? c->d_blk + blk_off[b] : nullptr;
     in.lz = mixed ? c->d_lz + lz_off[b] : nullptr;
+    in.sp = spectral ? c->d_spec + sp_off[b] : nullptr;
+    in.sp_ch0 = sp_ch0[b];
+    in.sp_nch = sp_nch[b];
   }
 
   // launch groups: one per configuration in use (trivial instances stop
@@ -521,7 +569,10 @@ sp2_status run_batch(sp2_ctx c) {
   c->square_ms.clear();
 
   SP2_HIP(c, hipEventRecord(c->ev_start, s));
-  SP2_HIP(c, sp2::launch_state_reset(c->d_st, count, c->d_ndone, s));
+  const bool spectral = (c->opt.norm == SP2_NORM_SPECTRAL) && c->spec_nchunks > 0;
+  SP2_HIP(c, sp2::launch_state_reset(c->d_st, count, c->d_ndone,
+                                     spectral ? c->d_spec_ctl : nullptr,
+                                     sp2::kMaxIter + 2, s));
   if (c->bsr) {
     SP2_HIP(c, sp2::launch_bsr_reset(c->b.ctr, s));
     SP2_HIP(c, sp2::launch_bsr_f0(c->b.F, c->b.m[0], c->b.nnzb_in, c->d_inst,
@@ -577,6 +628,17 @@ sp2_status run_batch(sp2_ctx c) {
       }
     }
     if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i + 1], s));
+    if (spectral) {
+      // e_{i-1} in the spectral norm, from X~_{i-1} (the squares' input)
+      sp2::SpecArgs sa;
+      sa.inst = c->d_inst;
+      sa.chunks = c->d_spec_chunks;
+      sa.nchunks = c->spec_nchunks;
+      sa.count = count;
+      sa.iter = i;
+      sa.ndone = c->d_spec_ctl + i;
+      SP2_HIP(c, sp2::launch_spectral(sa, c->fp64_store, c->spec_grid, s));
+    }
     SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
                                     c->d_ndone, c->mirror, i, s));
     SP2_HIP(c, hipEventRecord(c->ev_ring[i % kRing], s));
@@ -802,6 +864,9 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_sched);
   rel(c->d_blk);
   rel(c->d_lz);
+  rel(c->d_spec);
+  rel(c->d_spec_chunks);
+  rel(c->d_spec_ctl);
   rel(c->s_pool);
   rel(c->s_split[0]);
   rel(c->s_split[1]);
@@ -893,6 +958,10 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   if (st != SP2_OK) return st;
   if (opt.precision != SP2_FP32)
     return fail(c, SP2_INVALID_ARG, "block-sparse runs use SP2_FP32",
+                hipSuccess);
+  if (opt.norm == SP2_NORM_SPECTRAL)
+    return fail(c, SP2_INVALID_ARG,
+                "block-sparse runs use the Frobenius or the mixed norm",
                 hipSuccess);
   if (block != sp2::kBsrBlock)
     return fail(c, SP2_INVALID_ARG, "block must be 32", hipSuccess);
@@ -1248,8 +1317,18 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
 sp2_status sp2_get_mixed_history(sp2_ctx c, int32_t index, int32_t cap,
                                  int32_t* len, double* m) {
   if (!c) return SP2_INVALID_ARG;
-  if (!c->ran || c->opt.norm != SP2_NORM_MIXED)
-    return fail(c, SP2_BAD_STATE, "no completed run with the mixed norm",
+  if (c->ran && c->opt.norm != SP2_NORM_MIXED)
+    return fail(c, SP2_BAD_STATE, "the last run did not use the mixed norm",
+                hipSuccess);
+  return sp2_get_norm_history(c, index, cap, len, m);
+}
+
+sp2_status sp2_get_norm_history(sp2_ctx c, int32_t index, int32_t cap,
+                                int32_t* len, double* m) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran || c->opt.norm == SP2_NORM_FROBENIUS)
+    return fail(c, SP2_BAD_STATE,
+                "no completed run with the mixed or the spectral norm",
                 hipSuccess);
   if (index < 0 || index >= static_cast<int32_t>(c->host_state.size()) ||
       cap < 0)

@@ -47,7 +47,9 @@ struct DevState {
   int8_t p[kMaxIter + 2];
   double alpha[kMaxIter + 2];
   double v[kMaxIter + 1];
-  double m[kMaxIter + 1];   // mixed norm ||X~_k - X~_k^2||_M (mixed mode)
+  // ||X~_k - X~_k^2|| in the norm the stop reads when it is not the
+  // Frobenius norm: the mixed norm, or the spectral norm of Alg. 2
+  double m[kMaxIter + 1];
   // McWeeny (sec. 3): the stretch's beta, whether the stretch is on, and
   // the first step whose error the stop may test (0: none yet)
   double mw_beta;
@@ -75,7 +77,7 @@ struct StopParams {
   int32_t max_iter;  // squares allowed
   int32_t n_min;     // schedule: first step where the stop is tested
   int32_t n_max;     // schedule length; 0 = no schedule (Alg. 2 branch)
-  int32_t norm;      // error fed to the stop: 0 Frobenius, 1 mixed
+  int32_t norm;      // error fed to the stop: 0 Frobenius, 1 mixed, 2 spectral
   int32_t method;    // 0 SP2 (Alg. 2, or Alg. 4 with a schedule), 1 McWeeny
   int32_t mw_acc;    // McWeeny: 1 = McW-ACC with mw_beta0
   int32_t pad;
@@ -99,6 +101,47 @@ __host__ __device__ __forceinline__ MwCoef mw_coef(double a) {
 // largest Krylov dimension used to find its spectral norm.
 constexpr int kMixedBlock = 32;
 constexpr int kLanczosMax = 64;
+
+// Spectral norm of X~ - X~^2 (Alg. 2's e_i) by Lanczos: rows of X~ per work
+// chunk, and the per-instance scratch of the process (FP64). ldq is the
+// dimension rounded up to whole chunks; vectors are zero past n.
+constexpr int kSpecRows = 32;
+struct SpecView {
+  double* Q;      // kLanczosMax x ldq: the Lanczos basis q_0, q_1, ...
+  double* y;      // ldq: X~ q_j
+  double* w;      // ldq: E q_j, then orthogonalised against the basis
+  double* c1;     // nch x kLanczosMax: first Gram-Schmidt pass, per chunk
+  double* c2;     // nch x kLanczosMax: second pass
+  double* nrm;    // nch: squared norm of w over each chunk
+  double* ta;     // kLanczosMax: diagonal of the Lanczos tridiagonal
+  double* tb;     // kLanczosMax: its off-diagonal
+  double* misc;   // [0] previous estimate, [1] nonzero once final
+};
+__host__ __device__ __forceinline__ int spec_ldq(int n) {
+  return (n + kSpecRows - 1) / kSpecRows * kSpecRows;
+}
+__host__ __device__ __forceinline__ size_t spec_doubles(int n) {
+  const size_t ldq = static_cast<size_t>(spec_ldq(n));
+  const size_t nch = ldq / kSpecRows;
+  const size_t d = kLanczosMax * ldq + 2 * ldq + 2 * nch * kLanczosMax + nch +
+                   2 * kLanczosMax + 2;
+  return (d + 31) / 32 * 32;   // 256-byte aligned blocks
+}
+__host__ __device__ __forceinline__ SpecView spec_view(double* base, int n) {
+  const size_t ldq = static_cast<size_t>(spec_ldq(n));
+  const size_t nch = ldq / kSpecRows;
+  SpecView v;
+  v.Q = base;
+  v.y = v.Q + kLanczosMax * ldq;
+  v.w = v.y + ldq;
+  v.c1 = v.w + ldq;
+  v.c2 = v.c1 + nch * kLanczosMax;
+  v.nrm = v.c2 + nch * kLanczosMax;
+  v.ta = v.nrm + nch;
+  v.tb = v.ta + kLanczosMax;
+  v.misc = v.tb + kLanczosMax;
+  return v;
+}
 
 // Step i's polynomial written in the square S = X~_{i-1}^2 that the step
 // computes: X_i = ca S + cb X~_{i-1} + cc I. Alg. 4: p = 1 expands
@@ -150,6 +193,10 @@ struct Instance {
   int pad_blk;
   const int32_t* brp[2];
   const int32_t* bcol[2];
+  // Spectral norm (null unless prm.norm == 2): Lanczos scratch (spec_view)
+  // and the instance's range in the chunk table of the spectral launch
+  double* sp;
+  int sp_ch0, sp_nch;
 };
 
 // One unit of work of a square launch, given per workgroup by the host:
@@ -215,9 +262,27 @@ struct SquareArgs {
   int* bcnt;      // per tail tile: bands finished (0 between launches)
 };
 
+// Arguments of one spectral-norm launch: every running instance with a
+// chunk table entry (instance, first row) per kSpecRows rows.
+struct SpecArgs {
+  const Instance* inst;
+  const int2* chunks;
+  int nchunks;
+  int count;          // instances of the batch
+  int iter;           // step i: the norm of X~_{i-1}, written to m[i-1]
+  int32_t* ndone;     // instances whose estimate is final (zero at launch)
+};
+
 // Host-side launchers (implemented in the .hip files).
+// Clears the states and the batch's done counter; `zero` (may be null)
+// names `nzero` further counters to clear.
 hipError_t launch_state_reset(DevState* st, int count, int32_t* ndone,
-                              hipStream_t s);
+                              int32_t* zero, int nzero, hipStream_t s);
+// One cooperative launch of `grid` workgroups (at most spectral_max_grid).
+hipError_t launch_spectral(const SpecArgs& a, bool fp64_store, int grid,
+                           hipStream_t s);
+// Workgroups of the spectral kernel that fit on the device at once.
+int spectral_max_grid(bool fp64_store, int num_cus);
 hipError_t launch_f0(const Instance* inst, const F0Item* items, int nitems,
                      bool fp64_store, double* part_f0, hipStream_t s);
 hipError_t launch_finalize(const Instance* inst, int count,

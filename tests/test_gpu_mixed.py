@@ -145,7 +145,7 @@ def test_mixed_norm_argument_errors():
     with pytest.raises(sp2.SP2Error) as e:     # Frobenius run: no mixed history
         ctx.get_mixed_history()
     assert e.value.status == sp2.BAD_STATE
-    for norm, reserved in ((2, 0), (-1, 0), (0, 1)):
+    for norm, reserved in ((3, 0), (-1, 0), (0, 1)):
         opt = sp2.Options()
         lib.sp2_default_options(ctypes.byref(opt))
         opt.norm, opt.reserved = norm, reserved
