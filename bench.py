@@ -284,8 +284,8 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=0,
                     help="square-kernel configuration id (0 = library choice)")
     ap.add_argument("--no-acc", action="store_true",
-                    help="skip the SP2-ACC, McWeeny and McW-ACC comparison runs "
-                         "(dense workload)")
+                    help="skip the SP2-ACC, McWeeny, McW-ACC, mixed- and "
+                         "spectral-norm comparison runs (dense workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB twice with torch (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -487,6 +487,36 @@ def main() -> int:
                 "steps": stepsm, "matrix_products": 2 * stepsm,
                 "status": sp2.STATUS_NAMES[stm], "err_fro_vs_exact_D": errm,
             }
+
+    if not args.no_acc:
+        # The stop on the mixed and on the spectral norm (sec. 2; the spectral
+        # norm is Alg. 2's e_i), same input and precision. The spectral
+        # estimate is Lanczos on X~ - X~^2 with two products with the stored
+        # iterate per Lanczos step: algorithmic bytes = 2 N^2 w per step.
+        Qo = inst.Q[:, :inst.n_occ]
+        w_bytes = 8 if prec == "fp64" else 4
+        for norm in ("mixed", "spectral"):
+            log(f"[bench] {norm}-norm comparison run")
+            ctx.init_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,
+                           precision=prec, norm=norm, kernel_timing=True)
+            stn = ctx.run()
+            nn, sqn, msn = ctx.get_info()
+            e, ks = ctx.get_norm_history(krylov=True)
+            Dn = ctx.get_density(as_fp64=True).cpu().numpy()
+            errn = float(np.linalg.norm(Dn - Qo @ Qo.T))
+            del Dn
+            leg = {"time_to_D_ms": round(msn, 3), "n_iter": nn, "n_squares": sqn,
+                   "status": sp2.STATUS_NAMES[stn], "err_fro_vs_exact_D": errn,
+                   "lanczos_steps": int(sum(ks))}
+            if norm == "spectral":
+                nt = ctx.get_norm_times()
+                lz_ms = float(sum(nt))
+                mv_bytes = float(sum(ks)) * 2.0 * n * n * w_bytes
+                leg.update({"lanczos_ms": round(lz_ms, 3),
+                            "matvec_bytes": mv_bytes,
+                            "matvec_gbps": round(mv_bytes / (lz_ms * 1e-3) / 1e9, 1),
+                            "frac_of_hbm_peak": round(mv_bytes / (lz_ms * 1e-3) / 8e12, 4)})
+            out[f"norm_{norm}"] = leg
 
     if not args.no_cpu:
         log(f"[bench] CPU oracle sample ({args.cpu_squares} squares)")

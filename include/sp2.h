@@ -201,10 +201,13 @@ sp2_status sp2_get_mixed_history(sp2_ctx ctx, int32_t index, int32_t cap,
  * spectral norm: e[k] = ||X~_k - X~_k^2|| in that norm for
  * k = 0..n_squares-1 (sec. 2; Alg. 2 for the spectral norm), same
  * conventions as sp2_get_mixed_history; the Frobenius norms stay available
- * through sp2_get_history. Errors: SP2_BAD_STATE before a run or after a
- * Frobenius-norm run, SP2_INVALID_ARG. */
+ * through sp2_get_history. krylov[k] receives the number of Lanczos steps
+ * behind e[k] (each step of the spectral norm is two products with X~_k).
+ * e and krylov are host arrays of capacity `cap` and may be NULL. Errors:
+ * SP2_BAD_STATE before a run or after a Frobenius-norm run,
+ * SP2_INVALID_ARG. */
 sp2_status sp2_get_norm_history(sp2_ctx ctx, int32_t index, int32_t cap,
-                                int32_t* len, double* e);
+                                int32_t* len, double* e, int32_t* krylov);
 
 /* Per-step history of the last run, host arrays of capacity `cap`:
  * v[k] = ||X~_k - X~_k^2||_F for k = 0..n_squares-1; t1[k] = Tr X~_k and
@@ -224,6 +227,14 @@ sp2_status sp2_get_history(sp2_ctx ctx, int32_t cap, int32_t* len, double* v,
  * steps of the longest instance. *len receives that step count. ms may be
  * NULL. Errors: SP2_BAD_STATE when the last run did not record timings. */
 sp2_status sp2_get_kernel_times(sp2_ctx ctx, int32_t cap, int32_t* len,
+                                float* ms);
+
+/* Device durations (milliseconds, HIP events on the context's stream) of the
+ * spectral-norm launches of the last run, which must have used
+ * SP2_NORM_SPECTRAL and kernel_timing: ms[i] covers the Lanczos estimate of
+ * e_i (all instances). *len receives the step count. ms may be NULL.
+ * Errors: SP2_BAD_STATE otherwise. */
+sp2_status sp2_get_norm_times(sp2_ctx ctx, int32_t cap, int32_t* len,
                                 float* ms);
 
 /* ---- Block-sparse purification: the iterates are kept in block-sparse

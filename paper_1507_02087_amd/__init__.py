@@ -46,8 +46,11 @@ SIGNATURES = {
                                         _c.c_void_p]),
     "sp2_get_mixed_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
                                          _c.POINTER(_c.c_int32), _c.c_void_p]),
+    "sp2_get_norm_times": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.POINTER(_c.c_int32),
+                                      _c.c_void_p]),
     "sp2_get_norm_history": (_c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32,
-                                        _c.POINTER(_c.c_int32), _c.c_void_p]),
+                                        _c.POINTER(_c.c_int32), _c.c_void_p,
+                                        _c.c_void_p]),
     "sp2_init_bsr": (_c.c_int, [_c.c_void_p, _c.c_int64, _c.c_int32, _c.c_int64,
                                 _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_double,
                                 _c.c_double, _c.c_int64, _c.c_void_p]),
@@ -308,20 +311,31 @@ class Context:
 
     def get_mixed_history(self, index: int = 0):
         """m[k] = mixed norm of X~_k - X~_k^2 of the last run (norm="mixed")."""
-        return self._norm_history("sp2_get_mixed_history", index)
-
-    def get_norm_history(self, index: int = 0):
-        """e[k] = ||X~_k - X~_k^2|| in the norm the stop read (norm="mixed"
-        or "spectral") of the last run."""
-        return self._norm_history("sp2_get_norm_history", index)
-
-    def _norm_history(self, fn: str, index: int):
         import numpy as np
         ln = ctypes.c_int32()
         m = np.full(MAX_ITER_LIMIT + 1, np.nan)
-        self._check(getattr(self._lib, fn)(self._h, index, m.size, ctypes.byref(ln),
-                                           ctypes.c_void_p(m.ctypes.data)), fn)
+        self._check(self._lib.sp2_get_mixed_history(self._h, index, m.size,
+                                                    ctypes.byref(ln),
+                                                    ctypes.c_void_p(m.ctypes.data)),
+                    "sp2_get_mixed_history")
         return m[:ln.value].tolist()
+
+    def get_norm_history(self, index: int = 0, krylov: bool = False):
+        """e[k] = ||X~_k - X~_k^2|| in the norm the stop read (norm="mixed"
+        or "spectral") of the last run; with krylov=True also the Lanczos
+        steps behind each e[k]."""
+        import numpy as np
+        ln = ctypes.c_int32()
+        e = np.full(MAX_ITER_LIMIT + 1, np.nan)
+        ks = np.zeros(MAX_ITER_LIMIT + 1, dtype=np.int32)
+        self._check(self._lib.sp2_get_norm_history(self._h, index, e.size,
+                                                   ctypes.byref(ln),
+                                                   ctypes.c_void_p(e.ctypes.data),
+                                                   ctypes.c_void_p(ks.ctypes.data)),
+                    "sp2_get_norm_history")
+        if krylov:
+            return e[:ln.value].tolist(), ks[:ln.value].astype(int).tolist()
+        return e[:ln.value].tolist()
 
     def get_config(self, index: int = 0):
         """(id, name) of the square-kernel configuration instance `index`
@@ -341,6 +355,17 @@ class Context:
         self._check(self._lib.sp2_get_kernel_times(self._h, buf.size, ctypes.byref(ln),
                                                    ctypes.c_void_p(buf.ctypes.data)),
                     "sp2_get_kernel_times")
+        return buf[:ln.value].astype(float).tolist()
+
+    def get_norm_times(self):
+        """Spectral-norm launch durations (ms) of the last run with
+        kernel_timing and norm="spectral"."""
+        import numpy as np
+        ln = ctypes.c_int32()
+        buf = np.zeros(MAX_ITER_LIMIT + 1, dtype=np.float32)
+        self._check(self._lib.sp2_get_norm_times(self._h, buf.size, ctypes.byref(ln),
+                                                 ctypes.c_void_p(buf.ctypes.data)),
+                    "sp2_get_norm_times")
         return buf[:ln.value].astype(float).tolist()
 
     def get_history(self, cap: int = MAX_ITER_LIMIT + 2):

@@ -154,7 +154,7 @@ constexpr double kLanczosTol = 1e-12; // relative change of the top Ritz value
 // and receives the result.
 __device__ double mixed_norm(const Instance& in, int iter, double* w,
                              double* c, double* ta, double* tb, int* hits,
-                             double* red) {
+                             double* red, int* steps) {
   const int nb = in.nbk;
   const bool sparse = (in.brp[0] != nullptr);
   const int32_t* rp = sparse ? in.brp[iter & 1] : nullptr;
@@ -171,11 +171,13 @@ __device__ double mixed_norm(const Instance& in, int iter, double* w,
     for (int i = threadIdx.x; i < nb; i += kThreads) {
       double acc = 0.0;
       if (sparse) {
+#pragma unroll 4
         for (int q = rp[i]; q < rp[i + 1]; ++q)
           acc += static_cast<double>(in.blk[q]) * qj[col[q]];
       } else {
         // M is symmetric: walk column i so that neighbouring threads read
-        // neighbouring addresses
+        // neighbouring addresses; the loads of 16 rows go out together
+#pragma unroll 16
         for (int l = 0; l < nb; ++l)
           acc += static_cast<double>(in.blk[static_cast<size_t>(l) * nb + i]) *
                  qj[l];
@@ -197,6 +199,7 @@ __device__ double mixed_norm(const Instance& in, int iter, double* w,
       if (pass == 0 && threadIdx.x == 0) ta[j] = c[j];
       for (int i = threadIdx.x; i < nb; i += kThreads) {
         double x = w[i];
+#pragma unroll 8
         for (int l = 0; l <= j; ++l) x -= c[l] * Q[static_cast<size_t>(l) * nb + i];
         w[i] = x;
       }
@@ -218,6 +221,7 @@ __device__ double mixed_norm(const Instance& in, int iter, double* w,
     double* qn = Q + static_cast<size_t>(j + 1) * nb;
     for (int i = threadIdx.x; i < nb; i += kThreads) qn[i] = w[i] / beta;
   }
+  *steps = m;
   return theta;
 }
 
@@ -262,11 +266,12 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   block_sum3(a, b, c, sh);
   const StopParams& prm = in.prm;
   double mk = 0.0;
+  int mk_steps = 0;
   if (iter >= 1 && prm.norm == 1) {
     __shared__ double wv[kMaxBlockRows], cf[kLanczos], ta[kLanczos],
         tb[kLanczos], red[kThreads / 64];
     __shared__ int hits[kThreads];
-    mk = mixed_norm(in, iter, wv, cf, ta, tb, hits, red);
+    mk = mixed_norm(in, iter, wv, cf, ta, tb, hits, red, &mk_steps);
   }
   if (threadIdx.x != 0) return;
 
@@ -288,7 +293,10 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     const int k = iter - 1;
     const double vk = sqrt(a);
     st->v[k] = vk;
-    if (prm.norm == 1) st->m[k] = mk;   // the spectral kernel wrote m[k]
+    if (prm.norm == 1) {   // the spectral kernel writes m[k] itself
+      st->m[k] = mk;
+      st->krylov[k] = mk_steps;
+    }
     st->squares = iter;
     // the error the stop test reads: Frobenius, mixed or spectral (sec. 2)
     const double* e = (prm.norm != 0) ? st->m : st->v;

@@ -118,6 +118,7 @@ struct sp2_ctx_s {
   size_t d_spec_ctl_cap = 0;
   int spec_nchunks = 0;
   int spec_grid = 0;
+  int spec_vec_cap = 0;
   DevState* d_st = nullptr;
   size_t d_st_cap = 0;
   int2* d_tiles = nullptr;
@@ -141,6 +142,8 @@ struct sp2_ctx_s {
   hipEvent_t ev_ring[kRing] = {};
   std::vector<hipEvent_t> ev_sq;   // pairs around each step's squares
   std::vector<float> square_ms;
+  std::vector<hipEvent_t> ev_nm;   // pairs around each step's spectral launch
+  std::vector<float> norm_ms;
   bool timed = false;
 
   // block-sparse mode
@@ -413,16 +416,28 @@ sp2_status setup(sp2_ctx c) {
     SP2_HIP(c, grow(c->d_spec_chunks, c->d_spec_chunks_cap,
                     std::max<size_t>(1, chunks.size()) * sizeof(int2), s));
     SP2_HIP(c, grow(c->d_spec_ctl, c->d_spec_ctl_cap,
-                    (sp2::kMaxIter + 2) * sizeof(int32_t), s));
+                    (sp2::kMaxIter + 2) * sp2::kSpecCtl * sizeof(int32_t), s));
     if (!chunks.empty())
       SP2_HIP(c, hipMemcpyAsync(c->d_spec_chunks, chunks.data(),
                                 chunks.size() * sizeof(int2),
                                 hipMemcpyHostToDevice, s));
-    const int gmax = sp2::spectral_max_grid(c->fp64_store, c->num_cus);
+    // the product's input vector is staged in LDS for rows of up to
+    // kSpecLdsVec entries
+    int max_ldq = 0;
+    for (int b = 0; b < count; ++b)
+      if (!c->hi[b].trivial)
+        max_ldq = std::max(max_ldq, sp2::spec_ldq(static_cast<int>(c->hi[b].n)));
+    c->spec_vec_cap = std::min(max_ldq, sp2::kSpecLdsVec);
+    const int gmax =
+        sp2::spectral_max_grid(c->fp64_store, c->num_cus, c->spec_vec_cap);
     if (gmax < 1)
       return fail(c, SP2_HIP_ERROR, "spectral kernel: no co-resident grid",
                   hipGetLastError());
-    c->spec_grid = std::min<int>(gmax, static_cast<int>(chunks.size()));
+    // one workgroup per chunk, plus spare workgroups (one per instance at
+    // most) that take the small eigenvalue problems off the products' path
+    int active = 0;
+    for (int b = 0; b < count; ++b) active += c->hi[b].trivial ? 0 : 1;
+    c->spec_grid = std::min<int>(gmax, static_cast<int>(chunks.size()) + active);
   }
   c->spec_nchunks = static_cast<int>(chunks.size());
 
@@ -567,12 +582,17 @@ sp2_status run_batch(sp2_ctx c) {
   }
   c->timed = false;
   c->square_ms.clear();
+  c->norm_ms.clear();
 
   SP2_HIP(c, hipEventRecord(c->ev_start, s));
   const bool spectral = (c->opt.norm == SP2_NORM_SPECTRAL) && c->spec_nchunks > 0;
+  if (timing && spectral && c->ev_nm.empty()) {
+    c->ev_nm.assign(2 * (SP2_MAX_ITER_LIMIT + 1), nullptr);
+    for (hipEvent_t& e : c->ev_nm) SP2_HIP(c, hipEventCreate(&e));
+  }
   SP2_HIP(c, sp2::launch_state_reset(c->d_st, count, c->d_ndone,
                                      spectral ? c->d_spec_ctl : nullptr,
-                                     sp2::kMaxIter + 2, s));
+                                     (sp2::kMaxIter + 2) * sp2::kSpecCtl, s));
   if (c->bsr) {
     SP2_HIP(c, sp2::launch_bsr_reset(c->b.ctr, s));
     SP2_HIP(c, sp2::launch_bsr_f0(c->b.F, c->b.m[0], c->b.nnzb_in, c->d_inst,
@@ -630,14 +650,17 @@ sp2_status run_batch(sp2_ctx c) {
     if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i + 1], s));
     if (spectral) {
       // e_{i-1} in the spectral norm, from X~_{i-1} (the squares' input)
+      if (timing) SP2_HIP(c, hipEventRecord(c->ev_nm[2 * i], s));
       sp2::SpecArgs sa;
       sa.inst = c->d_inst;
       sa.chunks = c->d_spec_chunks;
       sa.nchunks = c->spec_nchunks;
       sa.count = count;
       sa.iter = i;
-      sa.ndone = c->d_spec_ctl + i;
+      sa.vec_cap = c->spec_vec_cap;
+      sa.ctl = c->d_spec_ctl + sp2::kSpecCtl * i;
       SP2_HIP(c, sp2::launch_spectral(sa, c->fp64_store, c->spec_grid, s));
+      if (timing) SP2_HIP(c, hipEventRecord(c->ev_nm[2 * i + 1], s));
     }
     SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
                                     c->d_ndone, c->mirror, i, s));
@@ -677,6 +700,10 @@ sp2_status run_batch(sp2_ctx c) {
       float t = 0.f;
       SP2_HIP(c, hipEventElapsedTime(&t, c->ev_sq[2 * i], c->ev_sq[2 * i + 1]));
       c->square_ms.push_back(t);
+      if (spectral) {
+        SP2_HIP(c, hipEventElapsedTime(&t, c->ev_nm[2 * i], c->ev_nm[2 * i + 1]));
+        c->norm_ms.push_back(t);
+      }
     }
     c->timed = true;
   }
@@ -887,6 +914,8 @@ sp2_status sp2_destroy(sp2_ctx c) {
   for (hipEvent_t e : c->ev_ring)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_sq)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_nm)
     if (e) (void)hipEventDestroy(e);
   delete c;
   return SP2_OK;
@@ -1320,11 +1349,11 @@ sp2_status sp2_get_mixed_history(sp2_ctx c, int32_t index, int32_t cap,
   if (c->ran && c->opt.norm != SP2_NORM_MIXED)
     return fail(c, SP2_BAD_STATE, "the last run did not use the mixed norm",
                 hipSuccess);
-  return sp2_get_norm_history(c, index, cap, len, m);
+  return sp2_get_norm_history(c, index, cap, len, m, nullptr);
 }
 
 sp2_status sp2_get_norm_history(sp2_ctx c, int32_t index, int32_t cap,
-                                int32_t* len, double* m) {
+                                int32_t* len, double* m, int32_t* krylov) {
   if (!c) return SP2_INVALID_ARG;
   if (!c->ran || c->opt.norm == SP2_NORM_FROBENIUS)
     return fail(c, SP2_BAD_STATE,
@@ -1338,6 +1367,8 @@ sp2_status sp2_get_norm_history(sp2_ctx c, int32_t index, int32_t cap,
   if (len) *len = cnt;
   if (m)
     for (int k = 0; k < cnt && k < cap; ++k) m[k] = h.m[k];
+  if (krylov)
+    for (int k = 0; k < cnt && k < cap; ++k) krylov[k] = h.krylov[k];
   return SP2_OK;
 }
 
@@ -1428,6 +1459,18 @@ sp2_status sp2_get_kernel_times(sp2_ctx c, int32_t cap, int32_t* len,
   if (len) *len = m;
   if (ms)
     for (int i = 0; i < cap && i < m; ++i) ms[i] = c->square_ms[i];
+  return SP2_OK;
+}
+
+sp2_status sp2_get_norm_times(sp2_ctx c, int32_t cap, int32_t* len,
+                              float* ms) {
+  if (!c) return SP2_INVALID_ARG;
+  if (!c->ran || !c->timed || c->opt.norm != SP2_NORM_SPECTRAL)
+    return SP2_BAD_STATE;
+  const int m = static_cast<int>(c->norm_ms.size());
+  if (len) *len = m;
+  if (ms)
+    for (int i = 0; i < cap && i < m; ++i) ms[i] = c->norm_ms[i];
   return SP2_OK;
 }
 

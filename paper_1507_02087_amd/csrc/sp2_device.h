@@ -50,6 +50,7 @@ struct DevState {
   // ||X~_k - X~_k^2|| in the norm the stop reads when it is not the
   // Frobenius norm: the mixed norm, or the spectral norm of Alg. 2
   double m[kMaxIter + 1];
+  int32_t krylov[kMaxIter + 1];   // Lanczos steps behind m[k]
   // McWeeny (sec. 3): the stretch's beta, whether the stretch is on, and
   // the first step whose error the stop may test (0: none yet)
   double mw_beta;
@@ -107,14 +108,13 @@ constexpr int kLanczosMax = 64;
 // dimension rounded up to whole chunks; vectors are zero past n.
 constexpr int kSpecRows = 32;
 struct SpecView {
-  double* Q;      // kLanczosMax x ldq: the Lanczos basis q_0, q_1, ...
-  double* y;      // ldq: X~ q_j
-  double* w;      // ldq: E q_j, then orthogonalised against the basis
-  double* c1;     // nch x kLanczosMax: first Gram-Schmidt pass, per chunk
-  double* c2;     // nch x kLanczosMax: second pass
-  double* nrm;    // nch: squared norm of w over each chunk
-  double* ta;     // kLanczosMax: diagonal of the Lanczos tridiagonal
-  double* tb;     // kLanczosMax: its off-diagonal
+  double* q;      // 2 x ldq: the last two Lanczos vectors (q_j in slot j % 2)
+  double* y;      // ldq: X~ u_j (u_j = beta_{j-1} q_j, not yet normalised)
+  double* w;      // ldq: E q_j - beta_{j-1} q_{j-1}
+  double* part;   // 2 x nch: per chunk q_j . w, by parity of j
+  double* nu;     // nch: per chunk u_j . u_j
+  double* ta;     // kLanczosMax: diagonal alpha_j of the Lanczos tridiagonal
+  double* tb;     // kLanczosMax: off-diagonal beta_j
   double* misc;   // [0] previous estimate, [1] nonzero once final
 };
 __host__ __device__ __forceinline__ int spec_ldq(int n) {
@@ -123,21 +123,19 @@ __host__ __device__ __forceinline__ int spec_ldq(int n) {
 __host__ __device__ __forceinline__ size_t spec_doubles(int n) {
   const size_t ldq = static_cast<size_t>(spec_ldq(n));
   const size_t nch = ldq / kSpecRows;
-  const size_t d = kLanczosMax * ldq + 2 * ldq + 2 * nch * kLanczosMax + nch +
-                   2 * kLanczosMax + 2;
+  const size_t d = 4 * ldq + 3 * nch + 2 * kLanczosMax + 4;
   return (d + 31) / 32 * 32;   // 256-byte aligned blocks
 }
 __host__ __device__ __forceinline__ SpecView spec_view(double* base, int n) {
   const size_t ldq = static_cast<size_t>(spec_ldq(n));
   const size_t nch = ldq / kSpecRows;
   SpecView v;
-  v.Q = base;
-  v.y = v.Q + kLanczosMax * ldq;
+  v.q = base;
+  v.y = v.q + 2 * ldq;
   v.w = v.y + ldq;
-  v.c1 = v.w + ldq;
-  v.c2 = v.c1 + nch * kLanczosMax;
-  v.nrm = v.c2 + nch * kLanczosMax;
-  v.ta = v.nrm + nch;
+  v.part = v.w + ldq;
+  v.nu = v.part + 2 * nch;
+  v.ta = v.nu + nch;
   v.tb = v.ta + kLanczosMax;
   v.misc = v.tb + kLanczosMax;
   return v;
@@ -270,19 +268,28 @@ struct SpecArgs {
   int nchunks;
   int count;          // instances of the batch
   int iter;           // step i: the norm of X~_{i-1}, written to m[i-1]
-  int32_t* ndone;     // instances whose estimate is final (zero at launch)
+  int vec_cap;        // doubles of dynamic LDS for the product's input vector
+  // kSpecCtl counters, zero at launch: [0] instances whose estimate is
+  // final
+  int32_t* ctl;
 };
+constexpr int kSpecCtl = 1;
+// Largest input vector (doubles) staged in LDS; longer rows read it from
+// global memory.
+constexpr int kSpecLdsVec = 8192;
 
 // Host-side launchers (implemented in the .hip files).
 // Clears the states and the batch's done counter; `zero` (may be null)
 // names `nzero` further counters to clear.
 hipError_t launch_state_reset(DevState* st, int count, int32_t* ndone,
                               int32_t* zero, int nzero, hipStream_t s);
-// One cooperative launch of `grid` workgroups (at most spectral_max_grid).
+// One cooperative launch of `grid` workgroups (at most spectral_max_grid)
+// with a.vec_cap doubles of dynamic LDS.
 hipError_t launch_spectral(const SpecArgs& a, bool fp64_store, int grid,
                            hipStream_t s);
-// Workgroups of the spectral kernel that fit on the device at once.
-int spectral_max_grid(bool fp64_store, int num_cus);
+// Workgroups of the spectral kernel that fit on the device at once with
+// vec_cap doubles of dynamic LDS each.
+int spectral_max_grid(bool fp64_store, int num_cus, int vec_cap);
 hipError_t launch_f0(const Instance* inst, const F0Item* items, int nitems,
                      bool fp64_store, double* part_f0, hipStream_t s);
 hipError_t launch_finalize(const Instance* inst, int count,

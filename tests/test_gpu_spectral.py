@@ -224,3 +224,30 @@ def test_spectral_argument_errors():
                       b.lambda_max, b.n_occ, norm="spectral")
     assert e.value.status == sp2.INVALID_ARG
     bctx.close()
+
+
+def test_spectral_krylov_and_timing():
+    """The Lanczos steps behind each estimate (1..64) and the per-step
+    duration of the spectral launch (HIP events) are reported."""
+    import torch
+    import paper_1507_02087_amd as sp2
+    inst = dense_instance(300, 150, -1.0, 1.0, 0.1, seed=31)
+    F = torch.from_numpy(inst.F).cuda()
+    ctx = sp2.Context(0)
+    ctx.init_dense(F, -1.0, 1.0, 150, precision="fp32", norm="spectral",
+                   kernel_timing=True)
+    assert ctx.run() == sp2.OK
+    e, ks = ctx.get_norm_history(krylov=True)
+    sq = ctx.get_info()[1]
+    assert len(e) == len(ks) == sq
+    assert all(1 <= k <= 64 for k in ks)
+    nt = ctx.get_norm_times()
+    assert len(nt) == sq and all(t > 0 for t in nt)
+    ctx.init_dense(F, -1.0, 1.0, 150, precision="fp32", norm="mixed", kernel_timing=True)
+    assert ctx.run() == sp2.OK
+    with pytest.raises(sp2.SP2Error) as err:   # no spectral launches timed
+        ctx.get_norm_times()
+    assert err.value.status == sp2.BAD_STATE
+    _, ks = ctx.get_norm_history(krylov=True)
+    assert all(1 <= k <= 64 for k in ks)
+    ctx.close()
