@@ -284,8 +284,11 @@ def main() -> int:
     ap.add_argument("--config", type=int, default=0,
                     help="square-kernel configuration id (0 = library choice)")
     ap.add_argument("--no-acc", action="store_true",
-                    help="skip the SP2-ACC, McWeeny, McW-ACC, mixed- and "
-                         "spectral-norm comparison runs (dense workload)")
+                    help="skip the SP2-ACC, McWeeny and McW-ACC comparison runs "
+                         "(dense workload)")
+    ap.add_argument("--no-norms", action="store_true",
+                    help="skip the mixed- and spectral-norm comparison runs "
+                         "(dense workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB twice with torch (a plain copy "
                          "kernel of known size, to scale HBM byte counters)")
@@ -488,7 +491,7 @@ def main() -> int:
                 "status": sp2.STATUS_NAMES[stm], "err_fro_vs_exact_D": errm,
             }
 
-    if not args.no_acc:
+    if not args.no_norms:
         # The stop on the mixed and on the spectral norm (sec. 2; the spectral
         # norm is Alg. 2's e_i), same input and precision. The spectral
         # estimate is Lanczos on X~ - X~^2 with two products with the stored
