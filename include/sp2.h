@@ -97,17 +97,17 @@ typedef enum {
                               as printed: dense and batched runs only. Found
                               by Lanczos on E = X~_k - X~_k^2 applied as
                               X~_k q - X~_k (X~_k q) to the stored iterate in
-                              FP64 arithmetic (E is never formed): full
-                              reorthogonalisation, at most 64 steps (two
-                              products with X~_k each), until the estimate
-                              max(|top|, |bottom| Ritz value) changes by
-                              < 1e-12 relative. The Ritz values lie inside
-                              E's spectrum, so the estimate never exceeds the
-                              norm; where E's top eigenvalues cluster (the
-                              first steps) it may stay below it by ~1e-4
-                              relative. One cooperative launch per step
-                              (every workgroup resident at once) runs the
-                              Lanczos processes of all instances */
+                              FP64 arithmetic (E is never formed): three-term
+                              recurrence with exact inner products, at most
+                              64 steps (two products with X~_k each), until
+                              the estimate max(|top|, |bottom| Ritz value)
+                              changes by < 1e-12 relative. The Ritz values
+                              lie inside E's spectrum, so the estimate never
+                              exceeds the norm; where E's top eigenvalues
+                              cluster (the first steps) it may stay below it
+                              by ~1e-4 relative. One cooperative launch per
+                              step (every workgroup resident at once) runs
+                              the Lanczos processes of all instances */
 } sp2_norm;
 
 /* Block edge of SP2_NORM_MIXED. */
