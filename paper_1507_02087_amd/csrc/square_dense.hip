@@ -838,13 +838,15 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   if (k0 + 1 < k1) s0.load(Ah, Al, Bh, Bl, ld, (k0 + 1) * C::BK, tid);
   if (k0 + 2 < k1) s1.load(Ah, Al, Bh, Bl, ld, (k0 + 2) * C::BK, tid);
   __syncthreads();
-  // one K slice: compute slice kt from LDS buffer b, store slice kt + 1
-  // (held in st) into the other buffer, refill st with slice kt + 3
+  // one K slice: store slice kt + 1 (held in st) into the other LDS buffer
+  // (last read in slice kt - 1, before the barrier that ended it), refill st
+  // with slice kt + 3, then compute slice kt from buffer b; the stores and
+  // the loads are issued before the slice's MFMAs instead of after them
   auto step = [&](int kt, St& st) {
     const int b = (kt - k0) & 1;
-    compute(b);
     if (kt + 1 < k1) sstore(st, b ^ 1);
     if (kt + 3 < k1) st.load(Ah, Al, Bh, Bl, ld, (kt + 3) * C::BK, tid);
+    compute(b);
     __syncthreads();
   };
   for (int kt = k0; kt < k1; kt += 2) {
@@ -881,7 +883,64 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
   const int wg = wave / C::WN, wn = (wave % C::WN) * C::TN;
   const bool split = (sc.Yh != nullptr);
   Sums sums;
+  // Thread tid owns column cc = tid % BM and the rows ph + R j of a band
+  // (ph = tid / BM): the elements e = tid + THREADS j in row-major order.
+  // Rows are visited one 32-row block at a time so that the block sums of
+  // the mixed norm are complete after each block row. The old iterate's (and
+  // in mode 2 the square's) values are loaded in batches of NB rows, each
+  // batch while the previous one is processed, and a band's first batch
+  // before its accumulators go to LDS.
+  const int cc = tid % BM, ph = tid / BM;
+  const int gc = J * BM + cc;
+  constexpr int NJ = kMixedBlock / R;   // rows of a block row per thread
+  constexpr int NB = (MODE == 2) ? (NJ < 8 ? NJ : 8) : (NJ < 16 ? NJ : 16);
+  constexpr int PER_RB = NJ / NB;
+  constexpr int NBATCH = (TM / kMixedBlock) * PER_RB;
+  static_assert(NJ % NB == 0 && NBATCH % 2 == 0, "load batches");
+  T xa[NB], sa[NB], xb[NB], sb[NB];
+  auto load_batch = [&](int r0, int bi, T* xv, T* sv) {
+    const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) {
+      const int gr = r0 + rb * kMixedBlock + ph + R * (j0 + jj);
+      const size_t idx = static_cast<size_t>(gr) * ld + gc;
+      const bool act = !(diag && gr > gc);
+      xv[jj] = act ? *gro(sc.X + idx) : T(0);
+      sv[jj] = (MODE == 2 && act) ? *gro(sc.Sr + idx) : T(0);
+    }
+  };
+  double bs = 0.0;
+  auto process = [&](int r0, int bi, const T* xv, const T* sv) {
+    const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) {
+      const int rr = rb * kMixedBlock + ph + R * (j0 + jj);
+      const int gr = r0 + rr;
+      if (!(diag && gr > gc)) {
+        const size_t idx = static_cast<size_t>(gr) * ld + gc;
+        const bool on = (gr == gc);
+        double d2;
+        const T xn = epilogue_elem<T, MODE>(S[rr * LD + cc], xv[jj], sv[jj],
+                                      sc.k, sc.tau, on ? 1.0 : 2.0,
+                                      on && gr < sc.n, sums, d2);
+        *grw(sc.Y + idx) = xn;
+        if (split) store_split(sc.Yh, sc.Yl, idx, xn);
+        S[rr * LD + cc] = xn;
+        bs += block_share(gr, gc, d2);
+      }
+    }
+    if ((bi + 1) % PER_RB == 0) {   // the block row is complete
+      if (sc.blk) {
+        // the 32 lanes of a half wave hold the 32 columns of one block
+        const double t = half_wave_sum(bs);
+        if ((lane & 31) == 0) bred[ph][rb][cc / kMixedBlock] = t;
+      }
+      bs = 0.0;
+    }
+  };
   for (int g = 0; g < C::WM; ++g) {
+    const int r0 = I * BM + g * TM;
+    load_batch(r0, 0, xa, sa);
     __syncthreads();
     if (wg == g) {
 #pragma unroll
@@ -896,37 +955,11 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
           }
     }
     __syncthreads();
-    const int r0 = I * BM + g * TM;
-    // Thread tid owns column cc = tid % BM and the rows ph + R j of the band
-    // (ph = tid / BM): the elements e = tid + THREADS j in row-major order.
-    // Rows are visited one 32-row block at a time so that the block sums of
-    // the mixed norm are complete after each block row.
-    const int cc = tid % BM, ph = tid / BM;
-    const int gc = J * BM + cc;
-    for (int rb = 0; rb < TM / kMixedBlock; ++rb) {
-      double bs = 0.0;
-      for (int jj = 0; jj < kMixedBlock / R; ++jj) {
-        const int rr = rb * kMixedBlock + ph + R * jj;
-        const int gr = r0 + rr;
-        if (!(diag && gr > gc)) {
-          const size_t idx = static_cast<size_t>(gr) * ld + gc;
-          const bool on = (gr == gc);
-          double d2;
-          const T sv = (MODE == 2) ? *gro(sc.Sr + idx) : T(0);
-          const T xn = epilogue_elem<T, MODE>(S[rr * LD + cc], *gro(sc.X + idx), sv,
-                                        sc.k, sc.tau, on ? 1.0 : 2.0,
-                                        on && gr < sc.n, sums, d2);
-          *grw(sc.Y + idx) = xn;
-          if (split) store_split(sc.Yh, sc.Yl, idx, xn);
-          S[rr * LD + cc] = xn;
-          bs += block_share(gr, gc, d2);
-        }
-      }
-      if (sc.blk) {
-        // the 32 lanes of a half wave hold the 32 columns of one block
-        bs = half_wave_sum(bs);
-        if ((lane & 31) == 0) bred[ph][rb][cc / kMixedBlock] = bs;
-      }
+    for (int bi = 0; bi < NBATCH; bi += 2) {
+      load_batch(r0, bi + 1, xb, sb);
+      process(r0, bi, xa, sa);
+      if (bi + 2 < NBATCH) load_batch(r0, bi + 2, xa, sa);
+      process(r0, bi + 1, xb, sb);
     }
     __syncthreads();
     if (sc.blk && tid < (TM / kMixedBlock) * (BM / kMixedBlock)) {
