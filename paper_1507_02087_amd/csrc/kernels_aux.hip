@@ -405,6 +405,44 @@ __global__ __launch_bounds__(kThreads) void copy_out_kernel(
   }
 }
 
+// D = X for a symmetric X of which only the upper triangle is current:
+// block (bi, bj) of 32 x 32 with bi <= bj reads the upper tile through LDS
+// and writes it and its transpose, both as rows (coalesced). Blocks with
+// bi > bj have nothing to do.
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(kThreads) void copy_out_sym_kernel(
+    const Tin* __restrict__ X, int n, int ldx, Tout* __restrict__ D,
+    int64_t ldd) {
+  constexpr int B = 32;
+  __shared__ Tin t[B][B + 1];
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  const int i0 = bi * B, j0 = bj * B;
+  for (int e = threadIdx.x; e < B * B; e += kThreads) {
+    const int r = e / B, c = e % B;
+    const int i = i0 + r, j = j0 + c;
+    if (i < n && j < n) t[r][c] = X[static_cast<int64_t>(i) * ldx + j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < B * B; e += kThreads) {
+    const int r = e / B, c = e % B;
+    const int i = i0 + r, j = j0 + c;
+    if (i < n && j < n) {
+      // on a diagonal tile the lower part comes from the transposed position
+      const Tin x = (bi == bj && r > c) ? t[c][r] : t[r][c];
+      D[static_cast<int64_t>(i) * ldd + j] = static_cast<Tout>(x);
+    }
+  }
+  if (bi == bj) return;
+  // the transpose: row j0 + r of D receives column r of the tile
+  for (int e = threadIdx.x; e < B * B; e += kThreads) {
+    const int r = e / B, c = e % B;
+    const int i = j0 + r, j = i0 + c;
+    if (i < n && j < n)
+      D[static_cast<int64_t>(i) * ldd + j] = static_cast<Tout>(t[c][r]);
+  }
+}
+
 int grid_for(int64_t total) {
   int64_t g = (total + kThreads - 1) / kThreads;
   if (g > 8192) g = 8192;
@@ -442,8 +480,25 @@ hipError_t launch_finalize(const Instance* inst, int count,
 }
 
 hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
-                           void* D, int64_t ldd, bool out_fp64,
+                           void* D, int64_t ldd, bool out_fp64, bool symmetric,
                            hipStream_t s) {
+  if (symmetric) {
+    const int nb = (n + 31) / 32;
+    const dim3 grid(nb, nb);
+    if (fp64_store)
+      hipLaunchKernelGGL((copy_out_sym_kernel<double, double>), grid,
+                         dim3(kThreads), 0, s, static_cast<const double*>(X), n,
+                         ldx, static_cast<double*>(D), ldd);
+    else if (out_fp64)
+      hipLaunchKernelGGL((copy_out_sym_kernel<float, double>), grid,
+                         dim3(kThreads), 0, s, static_cast<const float*>(X), n,
+                         ldx, static_cast<double*>(D), ldd);
+    else
+      hipLaunchKernelGGL((copy_out_sym_kernel<float, float>), grid,
+                         dim3(kThreads), 0, s, static_cast<const float*>(X), n,
+                         ldx, static_cast<float*>(D), ldd);
+    return hipGetLastError();
+  }
   const int g = grid_for(static_cast<int64_t>(n) * n);
   if (fp64_store) {
     hipLaunchKernelGGL((copy_out_kernel<double, double>), dim3(g),

@@ -607,6 +607,7 @@ sp2_status run_batch(sp2_ctx c) {
 
   sp2::SquareArgs a;
   a.mode = 0;
+  a.mirror32 = 1;
   a.inst = c->d_inst;
   a.tiles = c->d_tiles;
   a.ws = c->d_ws;
@@ -640,6 +641,10 @@ sp2_status run_batch(sp2_ctx c) {
     for (int mi = 0; mi < nmodes; ++mi) {
       a.mode = c->mcweeny ? mi + 1 : 0;
       for (const Group& g : c->groups) {
+        a.mirror32 = (!sp2::kernel_config(g.cfg)->presplit ||
+                      c->opt.norm == SP2_NORM_SPECTRAL)
+                         ? 1
+                         : 0;
         a.items = g.items;
         a.tails = g.tails;
         a.ntail = g.ntail;
@@ -750,9 +755,13 @@ sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
   const size_t esz = c->fp64_store ? 8 : 4;
   const void* X = static_cast<const char*>(c->pool[st.n & 1]) + h.xoff * esz;
   SP2_HIP(c, hipSetDevice(c->device));
+  // configurations with presplit operands leave the FP32 iterate's lower
+  // triangle unwritten unless the spectral norm reads it
+  const bool sym = sp2::kernel_config(h.cfg)->presplit &&
+                   c->opt.norm != SP2_NORM_SPECTRAL;
   SP2_HIP(c, sp2::launch_copy_out(X, c->fp64_store, static_cast<int>(h.n),
                                   static_cast<int>(h.np), D_dev, ldd,
-                                  as_fp64 != 0, c->stream));
+                                  as_fp64 != 0, sym, c->stream));
   SP2_HIP(c, hipStreamSynchronize(c->stream));
   return SP2_OK;
 }

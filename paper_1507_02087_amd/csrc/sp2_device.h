@@ -241,6 +241,9 @@ struct KernelConfig {
   int threads;     // workgroup size
   int occupancy;   // workgroups per CU the configuration is built for
   const char* name;  // family, tile, waves and K slice, e.g. "B3P_256_2x4_32"
+  // 1: the main loop reads only the bf16 split of the iterate, so the FP32
+  // iterate's lower triangle is not read by the next square
+  int presplit;
 };
 
 // Arguments of one square step of one launch group (instances sharing a
@@ -255,6 +258,10 @@ struct SquareArgs {
   int split;                  // pieces per tail tile
   int iter;                   // step i: X~_{i-1} -> X~_i
   int mode;                   // 0 SP2 step; McWeeny: 1 S = X~^2, 2 T = X~ S
+  // 1: the epilogues write the mirror (lower triangle) of the FP32 output;
+  // 0: only its bf16 split (configurations with presplit operands, when
+  // nothing else reads the FP32 lower triangle during the run)
+  int mirror32;
   double* part;   // 3 doubles per tile (global slot): ||X - S||_F^2, Tr, sum x^2
   double* bpart;  // 3 doubles per band of 32 rows of every tail tile
   int* bcnt;      // per tail tile: bands finished (0 between launches)
@@ -296,8 +303,10 @@ hipError_t launch_finalize(const Instance* inst, int count,
                            const double* part, const double* part_f0,
                            int32_t* ndone, HostMirror* mirror, int iter,
                            hipStream_t s);
+// symmetric = true rebuilds the lower triangle from the upper one (for
+// iterates whose FP32 mirror was not written).
 hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
-                           void* D, int64_t ldd, bool out_fp64,
+                           void* D, int64_t ldd, bool out_fp64, bool symmetric,
                            hipStream_t s);
 
 // ---- Block-sparse (BSR, 32 x 32 FP32 blocks) path.

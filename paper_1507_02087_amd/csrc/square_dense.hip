@@ -233,6 +233,7 @@ struct StepCtx {
   double tau;
   float* blk;     // block norms of X~_{i-1} - S (mixed norm), or null
   int nbk;
+  bool mirror32;  // write the FP32 output's lower triangle
 };
 
 template <typename T>
@@ -248,6 +249,7 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
   c.tau = in.tau;
   c.blk = in.blk;
   c.nbk = in.nbk;
+  c.mirror32 = a.mirror32 != 0;
   c.Sr = nullptr;
   if (a.mode == 0) {
     const StepCoef sc = step_coef(in.st->p[a.iter], in.st->alpha[a.iter]);
@@ -975,7 +977,7 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       if (diag && gr >= gc) continue;
       const size_t idt = static_cast<size_t>(gc) * ld + gr;
       const T xn = S[rr * LD + cc];
-      *grw(sc.Y + idt) = xn;
+      if (sc.mirror32) *grw(sc.Y + idt) = xn;
       if (split) store_split(sc.Yh, sc.Yl, idt, xn);
     }
   }
@@ -1218,7 +1220,7 @@ __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
     if (diag && gr >= gcc) continue;
     const size_t idt = static_cast<size_t>(gcc) * ld + gr;
     const T xn = band[rr][c];
-    *grw(sc.Y + idt) = xn;
+    if (sc.mirror32) *grw(sc.Y + idt) = xn;
     if (split) store_split(sc.Yh, sc.Yl, idt, xn);
   }
   // partial sums of the band, then of the tile
@@ -1306,10 +1308,20 @@ hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
 }
 
 template <class C>
+struct Presplit {
+  static constexpr int value = 0;
+};
+template <int A, int B, int Cc, int D>
+struct Presplit<CfgB3P<A, B, Cc, D>> {
+  static constexpr int value = 1;
+};
+
+template <class C>
 constexpr KernelConfig describe(int precision, int occupancy,
                                 const char* name) {
-  return KernelConfig{precision, C::BM, C::WM, C::WN, C::BK, C::THREADS,
-                      occupancy, name};
+  return KernelConfig{precision, C::BM, C::WM,     C::WN,
+                      C::BK,     C::THREADS, occupancy, name,
+                      Presplit<C>::value};
 }
 #define SP2_DESCRIBE(C, prec, occ) describe<C>(prec, occ, #C)
 

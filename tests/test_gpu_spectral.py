@@ -251,3 +251,23 @@ def test_spectral_krylov_and_timing():
     _, ks = ctx.get_norm_history(krylov=True)
     assert all(1 <= k <= 64 for k in ks)
     ctx.close()
+
+
+def test_spectral_with_presplit_config():
+    """The pre-split BF16x3 family normally leaves the FP32 iterate's lower
+    triangle unwritten (only its bf16 split is read by the next square);
+    with the spectral norm, whose products read whole rows of the iterate,
+    the mirror is written: the errors of the first steps match the FP32
+    oracle's, and D (rebuilt from the upper triangle otherwise) matches."""
+    import paper_1507_02087_amd as sp2
+    cfg = [c["id"] for c in sp2.kernel_configs() if c["name"] == "B3P_256_2x4_32"][0]
+    F, n_occ = _isolated_instance(300, seed=77)
+    print_case(f"spectral with presplit config {cfg}")
+    res = _run(F, -1.0, 1.0, n_occ, precision="bf16x3", max_iter=3, kernel_config=cfg)
+    ref = oracle.sp2(F, -1.0, 1.0, n_occ, norm="spectral", working="bf16x3", max_iter=3)
+    assert len(res.m) == 3
+    for j, (x, y) in enumerate(zip(res.m, ref.v)):
+        assert x == pytest.approx(y, rel=1e-3), (j, x, y)
+    D = res.D.cpu().numpy()
+    assert np.array_equal(D, D.T)
+    assert np.max(np.abs(D - ref.X)) < 1e-3
