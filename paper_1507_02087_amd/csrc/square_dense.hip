@@ -797,64 +797,94 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
       *reinterpret_cast<bf16x8*>(arr(b, 3) + o) = st.bl[q];
     }
   };
-  auto compute = [&](int b) {
+  // fragments of one MFMA k step (8 k per lane) of the slice in buffer b
+  struct Frag {
+    bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
+  };
+  auto fread = [&](Frag& f, int b, int s8) {
 #pragma unroll
-    for (int s8 = 0; s8 < C::KH; s8 += 8) {
-      bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m) {
-        const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
-        ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
-        al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
-      }
-#pragma unroll
-      for (int n = 0; n < C::NB; ++n) {
-        const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
-        bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
-        bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
-      }
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m], bh[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              ah[m], bl[n], acc.c[m][n], 0, 0, 0);
-#pragma unroll
-      for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-        for (int n = 0; n < C::NB; ++n)
-          acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              al[m], bh[n], acc.c[m][n], 0, 0, 0);
+    for (int m = 0; m < C::MB; ++m) {
+      const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
+      f.ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
     }
+#pragma unroll
+    for (int n = 0; n < C::NB; ++n) {
+      const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
+      f.bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
+      f.bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
+    }
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m) {
+      const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
+      f.al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
+    }
+  };
+  auto mma = [&](const Frag& f) {
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n)
+        acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            f.ah[m], f.bh[n], acc.c[m][n], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n)
+        acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            f.ah[m], f.bl[n], acc.c[m][n], 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m)
+#pragma unroll
+      for (int n = 0; n < C::NB; ++n)
+        acc.c[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            f.al[m], f.bh[n], acc.c[m][n], 0, 0, 0);
   };
   acc_zero<C>(acc);
   const int k0 = w.k0, k1 = w.k1;
+  // Loads and stores run unconditionally: a slice index past the last one
+  // is clamped to it (a harmless re-read whose store lands in a buffer no
+  // later slice reads). Branch-free loads let the compiler wait for just the
+  // older register set before storing it, not for every load in flight.
+  auto kc = [&](int kt) { return min(kt, k1 - 1) * C::BK; };
   s0.load(Ah, Al, Bh, Bl, ld, k0 * C::BK, tid);
   sstore(s0, 0);
-  if (k0 + 1 < k1) s0.load(Ah, Al, Bh, Bl, ld, (k0 + 1) * C::BK, tid);
-  if (k0 + 2 < k1) s1.load(Ah, Al, Bh, Bl, ld, (k0 + 2) * C::BK, tid);
+  // the scheduling fences keep each register set's loads together and in
+  // the same order as inside the loop
+  __builtin_amdgcn_sched_barrier(0);
+  s0.load(Ah, Al, Bh, Bl, ld, kc(k0 + 1), tid);
+  __builtin_amdgcn_sched_barrier(0);
+  s1.load(Ah, Al, Bh, Bl, ld, kc(k0 + 2), tid);
+  __builtin_amdgcn_sched_barrier(0);
   __syncthreads();
-  // one K slice: store slice kt + 1 (held in st) into the other LDS buffer
-  // (last read in slice kt - 1, before the barrier that ended it), refill st
-  // with slice kt + 3, then compute slice kt from buffer b; the stores and
-  // the loads are issued before the slice's MFMAs instead of after them
+  // one K slice: read the fragments of its first k step from buffer b,
+  // store slice kt + 1 (held in st) into the other LDS buffer (last read in
+  // slice kt - 1, before the barrier that ended it), refill st with slice
+  // kt + 3, then issue the MFMAs. The fragment reads go first: the LDS
+  // serves them ahead of the stores, so the MFMAs start without waiting for
+  // every wave's stores of the next slice.
   auto step = [&](int kt, St& st) {
     const int b = (kt - k0) & 1;
-    if (kt + 1 < k1) sstore(st, b ^ 1);
-    if (kt + 3 < k1) st.load(Ah, Al, Bh, Bl, ld, (kt + 3) * C::BK, tid);
-    compute(b);
+    Frag f;
+    fread(f, b, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    sstore(st, b ^ 1);
+    st.load(Ah, Al, Bh, Bl, ld, kc(kt + 3), tid);
+    mma(f);
+#pragma unroll
+    for (int s8 = 8; s8 < C::KH; s8 += 8) {
+      Frag g;
+      fread(g, b, s8);
+      mma(g);
+    }
     __syncthreads();
   };
-  for (int kt = k0; kt < k1; kt += 2) {
+  // pairs of slices, then an odd last one: no branch inside the loop body
+  int kt = k0;
+  for (; kt + 1 < k1; kt += 2) {
     step(kt, s0);
-    if (kt + 1 < k1) step(kt + 1, s1);
+    step(kt + 1, s1);
   }
+  if (kt < k1) step(kt, s0);
 }
 
 // Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
