@@ -887,13 +887,30 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   if (kt < k1) step(kt, s0);
 }
 
+// Stores the BF16x3 split of four consecutive values (8-byte stores).
+__device__ __forceinline__ void store_split4(__bf16* Yh, __bf16* Yl, size_t i,
+                                             floatx4 x) {
+  bf16x4 hi, lo;
+  split_bf16(x, hi, lo);
+  *grw(reinterpret_cast<bf16x4*>(Yh + i)) = hi;
+  *grw(reinterpret_cast<bf16x4*>(Yl + i)) = lo;
+}
+
+// Sum over the 8 lanes of an aligned lane octet (fixed order).
+__device__ __forceinline__ double octet_sum(double x) {
+  for (int off = 4; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
 // Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
 // (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
 // The tile is processed one band of TM rows at a time (the rows of one row
-// of waves): the waves of the band write their accumulators to LDS, then all
-// threads apply the element epilogue in row order (coalesced reads of X and
-// writes of the tile) and write the transposed band in row order of the
-// transpose (coalesced), reading LDS down columns (padding: no conflicts).
+// of waves): the waves of the band write their accumulators to LDS, then
+// every thread applies the element epilogue to runs of four consecutive
+// elements of a row (16-byte loads of the old iterate, 16-byte FP32 and
+// 8-byte bf16 stores, whole rows per group of threads) and writes runs of
+// four consecutive elements of the transposed band, read down the columns
+// of LDS (row stride BM + 1 words: at most two lanes per bank).
 template <class C, int MODE>
 __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
                                                  double* part, int slot,
@@ -901,9 +918,13 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
                                                  char* smem) {
   using T = float;
   constexpr int BM = C::BM, TM = C::TM, LD = BM + 1;
-  constexpr int R = C::THREADS / BM;   // rows of a band one pass covers
-  static_assert(C::THREADS % BM == 0 && kMixedBlock % R == 0 &&
-                    TM % kMixedBlock == 0 && BM % 64 == 0,
+  constexpr int V = 4;                   // consecutive elements per thread
+  constexpr int TPR = BM / V;            // threads per row of the tile
+  constexpr int R = C::THREADS / TPR;    // rows of a band one pass covers
+  constexpr int NJ = kMixedBlock / R;    // rows of a block row per thread
+  constexpr int BPT = kMixedBlock / V;   // threads per row of a block
+  static_assert(C::THREADS % TPR == 0 && kMixedBlock % R == 0 &&
+                    TM % kMixedBlock == 0 && TPR % BPT == 0 && 64 % BPT == 0,
                 "epilogue thread layout");
   __shared__ double bred[R][TM / kMixedBlock][BM / kMixedBlock];
   T* S = reinterpret_cast<T*>(smem);
@@ -915,61 +936,87 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
   const int wg = wave / C::WN, wn = (wave % C::WN) * C::TN;
   const bool split = (sc.Yh != nullptr);
   Sums sums;
-  // Thread tid owns column cc = tid % BM and the rows ph + R j of a band
-  // (ph = tid / BM): the elements e = tid + THREADS j in row-major order.
-  // Rows are visited one 32-row block at a time so that the block sums of
-  // the mixed norm are complete after each block row. The old iterate's (and
-  // in mode 2 the square's) values are loaded in batches of NB rows, each
-  // batch while the previous one is processed, and a band's first batch
-  // before its accumulators go to LDS.
-  const int cc = tid % BM, ph = tid / BM;
-  const int gc = J * BM + cc;
-  constexpr int NJ = kMixedBlock / R;   // rows of a block row per thread
-  constexpr int NB = (MODE == 2) ? (NJ < 8 ? NJ : 8) : (NJ < 16 ? NJ : 16);
+  // Thread tid owns columns c0 .. c0 + 3 (c0 = 4 (tid % TPR)) of the rows
+  // ph + R j of a band (ph = tid / TPR). Rows are visited one 32-row block at
+  // a time so that the block sums of the mixed norm are complete after each
+  // block row. The old iterate's (and in mode 2 the square's) values are
+  // loaded in batches of NB rows, each batch while the previous one is
+  // processed, and a band's first batch before its accumulators go to LDS.
+  const int c0 = (tid % TPR) * V, ph = tid / TPR;
+  const int gc0 = J * BM + c0;
+  constexpr int NB = (MODE == 2) ? (NJ < 2 ? NJ : 2) : NJ;
   constexpr int PER_RB = NJ / NB;
   constexpr int NBATCH = (TM / kMixedBlock) * PER_RB;
   static_assert(NJ % NB == 0 && NBATCH % 2 == 0, "load batches");
-  T xa[NB], sa[NB], xb[NB], sb[NB];
-  auto load_batch = [&](int r0, int bi, T* xv, T* sv) {
+  floatx4 xa[NB], sa[NB], xb[NB], sb[NB];
+  // in a diagonal tile, rows whose four elements all lie below the diagonal
+  // are neither loaded nor processed
+  auto load_batch = [&](int r0, int bi, floatx4* xv, floatx4* sv) {
     const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
       const int gr = r0 + rb * kMixedBlock + ph + R * (j0 + jj);
-      const size_t idx = static_cast<size_t>(gr) * ld + gc;
-      const bool act = !(diag && gr > gc);
-      xv[jj] = act ? *gro(sc.X + idx) : T(0);
-      sv[jj] = (MODE == 2 && act) ? *gro(sc.Sr + idx) : T(0);
+      const size_t idx = static_cast<size_t>(gr) * ld + gc0;
+      const bool any = !(diag && gr > gc0 + V - 1);
+      const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+      xv[jj] = any ? *gro(reinterpret_cast<const floatx4*>(sc.X + idx)) : z;
+      sv[jj] = (MODE == 2 && any)
+                   ? *gro(reinterpret_cast<const floatx4*>(sc.Sr + idx))
+                   : z;
     }
   };
   double bs = 0.0;
-  auto process = [&](int r0, int bi, const T* xv, const T* sv) {
+  auto process = [&](int r0, int bi, const floatx4* xv, const floatx4* sv) {
     const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
       const int rr = rb * kMixedBlock + ph + R * (j0 + jj);
       const int gr = r0 + rr;
-      if (!(diag && gr > gc)) {
-        const size_t idx = static_cast<size_t>(gr) * ld + gc;
-        const bool on = (gr == gc);
-        double d2;
-        const T xn = epilogue_elem<T, MODE>(S[rr * LD + cc], xv[jj], sv[jj],
-                                      sc.k, sc.tau, on ? 1.0 : 2.0,
-                                      on && gr < sc.n, sums, d2);
-        *grw(sc.Y + idx) = xn;
-        if (split) store_split(sc.Yh, sc.Yl, idx, xn);
-        S[rr * LD + cc] = xn;
-        bs += block_share(gr, gc, d2);
+      const size_t idx = static_cast<size_t>(gr) * ld + gc0;
+      if (diag && gr > gc0 + V - 1) continue;
+      floatx4 xn4;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const int gc = gc0 + i;
+        xn4[i] = T(0);
+        if (!(diag && gr > gc)) {
+          const bool on = (gr == gc);
+          double d2;
+          const T xn = epilogue_elem<T, MODE>(
+              S[rr * LD + c0 + i], xv[jj][i], sv[jj][i], sc.k, sc.tau,
+              on ? 1.0 : 2.0, on && gr < sc.n, sums, d2);
+          xn4[i] = xn;
+          S[rr * LD + c0 + i] = xn;
+          bs += block_share(gr, gc, d2);
+        }
+      }
+      if (!diag || gr <= gc0) {   // all four elements are processed
+        *grw(reinterpret_cast<floatx4*>(sc.Y + idx)) = xn4;
+        if (split) store_split4(sc.Yh, sc.Yl, idx, xn4);
+      } else {                    // the run crosses the diagonal
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (gr <= gc0 + i) {
+            *grw(sc.Y + idx + i) = xn4[i];
+            if (split) store_split(sc.Yh, sc.Yl, idx + i, xn4[i]);
+          }
       }
     }
     if ((bi + 1) % PER_RB == 0) {   // the block row is complete
       if (sc.blk) {
-        // the 32 lanes of a half wave hold the 32 columns of one block
-        const double t = half_wave_sum(bs);
-        if ((lane & 31) == 0) bred[ph][rb][cc / kMixedBlock] = t;
+        // the 8 lanes of an aligned octet hold the 32 columns of one block
+        const double t = octet_sum(bs);
+        if ((lane & (BPT - 1)) == 0) bred[ph][rb][c0 / kMixedBlock] = t;
       }
       bs = 0.0;
     }
   };
+  // transposed band: thread tid writes rows r4 .. r4 + 3 of the band (as
+  // four consecutive columns) into row oc of the transpose
+  constexpr int TPO = TM / V;             // threads per transposed row
+  constexpr int OPP = C::THREADS / TPO;   // transposed rows per pass
+  static_assert(C::THREADS % TPO == 0 && BM % OPP == 0, "mirror layout");
+  const int r4 = (tid % TPO) * V;
   for (int g = 0; g < C::WM; ++g) {
     const int r0 = I * BM + g * TM;
     load_batch(r0, 0, xa, sa);
@@ -1001,14 +1048,25 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       const int grb = r0 / kMixedBlock + rb, gcb = J * BM / kMixedBlock + cb;
       if (grb <= gcb) blk_write(sc.blk, sc.nbk, grb, gcb, t);
     }
-    for (int e = tid; e < TM * BM; e += C::THREADS) {
-      const int cc = e / TM, rr = e % TM;
-      const int gr = r0 + rr, gc = J * BM + cc;
-      if (diag && gr >= gc) continue;
-      const size_t idt = static_cast<size_t>(gc) * ld + gr;
-      const T xn = S[rr * LD + cc];
-      if (sc.mirror32) *grw(sc.Y + idt) = xn;
-      if (split) store_split(sc.Yh, sc.Yl, idt, xn);
+    const int gr0 = r0 + r4;
+    for (int oc = tid / TPO; oc < BM; oc += OPP) {
+      const int gc = J * BM + oc;
+      if (diag && gr0 >= gc) continue;   // all four on or below the diagonal
+      floatx4 v;
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = S[(r4 + i) * LD + oc];
+      const size_t idt = static_cast<size_t>(gc) * ld + gr0;
+      if (!diag || gr0 + V - 1 < gc) {
+        if (sc.mirror32) *grw(reinterpret_cast<floatx4*>(sc.Y + idt)) = v;
+        if (split) store_split4(sc.Yh, sc.Yl, idt, v);
+      } else {
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (gr0 + i < gc) {
+            if (sc.mirror32) *grw(sc.Y + idt + i) = v[i];
+            if (split) store_split(sc.Yh, sc.Yl, idt + i, v[i]);
+          }
+      }
     }
   }
   store_partials<C::THREADS>(sums, part, slot, MODE);
