@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   __shared__ double sh[kThreads / 64][3];
   const F0Item it = items[blockIdx.x];
   const Instance& in = insts[it.inst];
-  const int n = in.n, np = in.ld;
+  const int n = in.n, ld = in.ld;   // row stride (padded width)
   const int n_occ = static_cast<int>(in.prm.n_occ);
   const int trivial = (n_occ == 0) ? 1 : (n_occ == n ? 2 : 0);
   T* X = static_cast<T*>(in.X[0]);
@@ -92,8 +92,8 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   for (int rr = 0; rr < kF0Rows; ++rr) {
     const int i = it.row0 + rr;
     const double* Fi = in.F + static_cast<int64_t>(i) * in.ldf;
-    T* Xi = X + static_cast<int64_t>(i) * np;
-    for (int j = threadIdx.x; j < np; j += kThreads) {
+    T* Xi = X + static_cast<int64_t>(i) * ld;
+    for (int j = threadIdx.x; j < ld; j += kThreads) {
       double x = 0.0;
       if (i < n && j < n) {
         if (trivial) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
       if (XH) {
         const float xf = static_cast<float>(xs);
         const __bf16 hb = static_cast<__bf16>(xf);
-        const size_t o = static_cast<size_t>(i) * np + j;
+        const size_t o = static_cast<size_t>(i) * ld + j;
         XH[o] = hb;
         XL[o] = static_cast<__bf16>(xf - static_cast<float>(hb));
       }

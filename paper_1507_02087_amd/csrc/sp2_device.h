@@ -170,7 +170,8 @@ struct Instance {
   const double* F;     // input, FP64, row-major
   int64_t ldf;
   int n;               // matrix dimension
-  int ld;              // padded dimension (multiple of the tile edge)
+  int ld;              // row stride of the iterate buffers: the padded
+                       // dimension (multiple of the tile edge) or more
   int tile0, ntiles;   // range of this instance in the tile table
   int f0blk0, nf0blk;  // range of its affine-start blocks
   DevState* st;

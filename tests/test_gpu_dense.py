@@ -98,6 +98,30 @@ def test_one_square_elementwise(prec, cfg, n, split):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_one_square_padded_row_stride(prec):
+    """N = 2048: the library stores the iterate with a row stride longer
+    than the padded width (2048 is a multiple of 512), so this covers the
+    affine start, the square, its transposed writes and the copy-out at that
+    stride: X~_1 element by element against the oracle's step, symmetric,
+    and the traces."""
+    n = 2048
+    n_occ = n // 2
+    inst = dense_instance(n, n_occ, -1.0, 1.3, 0.1, seed=2048)
+    print_case(f"one square padded stride n={n} prec={prec}")
+    res = _run(inst.F, inst, precision=prec, max_iter=1)
+    ref = oracle.sp2(inst.F, inst.lambda_min, inst.lambda_max, n_occ,
+                     max_iter=1, working=prec)
+    assert res.status_name == "NOT_CONVERGED" and res.n == 1
+    assert res.p[1] == ref.p[1]
+    D = res.D.cpu().numpy()
+    tol = square_bound(n, prec) + (2.0 ** -22 if prec != "fp64" else 0.0)
+    err = float(np.max(np.abs(D - ref.X)))
+    assert err <= tol, (err, tol)
+    assert np.array_equal(D, D.T)
+    assert abs(res.t1[1] - ref.t1[1]) <= n * tol + 1e-12
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_full_run_small_config(prec):
     """Dense N=512, gap 0.1, n_occ 256: the stop is detected automatically
     and D matches the FP64 oracle within the stated Frobenius tolerance."""
