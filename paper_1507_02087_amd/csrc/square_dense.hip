@@ -422,6 +422,11 @@ struct CfgF32 {
   static constexpr int MB = TM / 32, NB = TN / 32;
   static constexpr int KH = BK / 2;     // k values per lane half per slice
   static constexpr int LDK = BK + 4;
+  // the main loop's two double-buffered operand arrays and the epilogue's
+  // band share one LDS allocation
+  static constexpr int MAIN_BYTES = 2 * 2 * BM * LDK * 4;
+  static constexpr int EPI_BYTES = TM * (BM + 1) * 4;
+  static constexpr int SMEM = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
   struct Acc {
     floatx16 c[MB][NB];
   };
@@ -430,10 +435,11 @@ struct CfgF32 {
 template <class C>
 __device__ __forceinline__ void mainloop_f32(const StepCtx<float>& sc,
                                              const WorkItem& w,
-                                             typename C::Acc& acc) {
+                                             typename C::Acc& acc,
+                                             char* smem) {
   using T = float;
-  __shared__ __attribute__((aligned(16))) T As[2][C::BM][C::LDK];
-  __shared__ __attribute__((aligned(16))) T Bs[2][C::BM][C::LDK];
+  T(*As)[C::BM][C::LDK] = reinterpret_cast<T(*)[C::BM][C::LDK]>(smem);
+  T(*Bs)[C::BM][C::LDK] = As + 2;
   const int2 tt = sc.tile;
   const int ld = sc.ld;
   const T* X = sc.X;
@@ -1132,16 +1138,16 @@ struct Ops<CfgF64<A, B, Cc, D>> {
 template <int A, int B, int Cc, int D>
 struct Ops<CfgF32<A, B, Cc, D>> {
   using C = CfgF32<A, B, Cc, D>;
-  static constexpr int kSmem = 16;
+  static constexpr int kSmem = C::SMEM;
   using T = typename C::T;
   __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc, char*) {
-    mainloop_f32<C>(sc, w, acc);
+                              typename C::Acc& acc, char* smem) {
+    mainloop_f32<C>(sc, w, acc, smem);
   }
   template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc, char*) {
-    epilogue_f32<C, MODE>(sc, part, slot, acc);
+                             const typename C::Acc& acc, char* smem) {
+    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
