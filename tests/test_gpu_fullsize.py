@@ -93,3 +93,73 @@ def test_full_run_against_exact_density():
         x = x * x if res.p[k + 1] == 1 else 2 * x - x * x
         checked += 1
     assert checked >= 5
+
+
+def test_batch_full_size():
+    """The 512-instance FP32 batch (N uniform in [64, 1024], seed 4001) as the
+    benchmark runs it: every instance stops by the test of Alg. 2 (the
+    branch alternates, r < 1.8), and every 16th instance's D is the exact
+    one within the FP32 tolerance."""
+    import torch
+
+    import paper_1507_02087_amd as sp2
+    from workloads import batch_instances
+    insts = batch_instances(count=512, seed=4001)
+    print_case("512-instance fp32 batch, full size")
+    Fs = [torch.from_numpy(i.F).to("cuda:0") for i in insts]
+    res, ms = sp2.run_batch(Fs, [i.lambda_min for i in insts], [i.lambda_max for i in insts],
+                            [i.n_occ for i in insts], precision="fp32")
+    worst = 0.0
+    for b, (inst, r) in enumerate(zip(insts, res)):
+        assert r.status == sp2.OK, (b, r.status)
+        assert r.p[r.n] != r.p[r.n - 1] and r.r[r.n] < 1.8, b
+        if b % 16 == 0:
+            De = oracle.density_from_eigenvectors(inst.Q, inst.n_occ)
+            err = float(np.linalg.norm(r.D.cpu().numpy() - De)) / math.sqrt(inst.n_occ)
+            worst = max(worst, err)
+            assert err <= 2e-5, (b, err)
+    print(f"  {ms:.2f} ms, worst sampled error {worst:.3e}", flush=True)
+
+
+def test_bsr_full_size():
+    """The block-sparse workload (banded N = 32768, 48 Givens layers, BSR
+    32 x 32 FP32, truncation 1e-6, seed 5001) as the benchmark runs it: the
+    stop of Alg. 2, the trace, and the distance from the exactly known D,
+    block row by block row."""
+    import torch
+
+    import paper_1507_02087_amd as sp2
+    from workloads.banded import banded_instance, to_bsr_blocks
+    n = 32768
+    inst = banded_instance(n=n, layers=48, seed=5001)
+    print_case(f"bsr n={n} full size")
+    rp, ci, bl = to_bsr_blocks(inst.F, 32)
+    ctx = sp2.BsrContext(0)
+    try:
+        ctx.init_bsr(n, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(bl)).cuda(),
+                     inst.lambda_min, inst.lambda_max, inst.n_occ, trunc_tau=1e-6)
+        st = ctx.run()
+        n_it, n_sq, ms = ctx.get_info()
+        hist = ctx.get_history()
+        rpo, cio, blo = (t.cpu().numpy() for t in ctx.get_bsr(as_fp64=True))
+    finally:
+        ctx.close()
+    assert st == sp2.OK
+    assert hist["p"][n_it] != hist["p"][n_it - 1] and hist["r"][n_it] < 1.8
+    De = inst.density_exact().tocsr()
+    err2, tr = 0.0, 0.0
+    for r in range(n // 32):
+        rows = De[32 * r:32 * r + 32].toarray()
+        got = np.zeros_like(rows)
+        for q in range(rpo[r], rpo[r + 1]):
+            c = cio[q]
+            assert q == rpo[r] or c > cio[q - 1]     # sorted block columns
+            got[:, 32 * c:32 * c + 32] = blo[q]
+            if c == r:
+                tr += float(np.trace(blo[q]))
+        err2 += float(np.sum((got - rows) ** 2))
+    err = math.sqrt(err2) / math.sqrt(inst.n_occ)
+    print(f"  n = {n_it}, {ms:.2f} ms, error {err:.3e}", flush=True)
+    assert err <= 1e-4, err
+    assert abs(tr - inst.n_occ) <= 1e-3 * math.sqrt(n)
