@@ -916,7 +916,9 @@ __device__ __forceinline__ double octet_sum(double x) {
 // elements of a row (16-byte loads of the old iterate, 16-byte FP32 and
 // 8-byte bf16 stores, whole rows per group of threads) and writes runs of
 // four consecutive elements of the transposed band, read down the columns
-// of LDS (row stride BM + 1 words: at most two lanes per bank).
+// of LDS. With a row stride of BM + 1 words the column reads put at most
+// two lanes of a wave on one bank and the row reads (lanes four words
+// apart) four; the epilogue's LDS traffic is small beside its stores.
 template <class C, int MODE>
 __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
                                                  double* part, int slot,
