@@ -1369,6 +1369,7 @@ using F64_64_2x2 = CfgF64<64, 2, 2, 16>;
 using F32_128_2x2 = CfgF32<128, 2, 2, 32>;
 using F32_128_2x4 = CfgF32<128, 2, 4, 32>;
 using F32_256_2x2 = CfgF32<256, 2, 2, 16>;
+using F32_256_2x4 = CfgF32<256, 2, 4, 32>;
 using B3_128_2x2 = CfgB3<128, 2, 2, 32>;
 using B3_256_2x2 = CfgB3<256, 2, 2, 16>;
 using B3_256_2x4 = CfgB3<256, 2, 4, 16>;
@@ -1431,7 +1432,7 @@ const KernelConfig kConfigs[] = {
     SP2_DESCRIBE(B3_256_2x4, 2, 1),  SP2_DESCRIBE(B3S_256_2x4, 2, 1),
     SP2_DESCRIBE(B3S_256_2x4_16, 2, 1), SP2_DESCRIBE(B3S_128_2x2, 2, 2),
     SP2_DESCRIBE(B3P_256_2x4, 2, 1), SP2_DESCRIBE(B3P_256_2x4_32, 2, 1),
-    SP2_DESCRIBE(B3P_128_2x2, 2, 2),
+    SP2_DESCRIBE(B3P_128_2x2, 2, 2), SP2_DESCRIBE(F32_256_2x4, 1, 1),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -1460,6 +1461,7 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 12: return launch_cfg<B3P_256_2x4>(a, grid, s);
     case 13: return launch_cfg<B3P_256_2x4_32>(a, grid, s);
     case 14: return launch_cfg<B3P_128_2x2>(a, grid, s);
+    case 15: return launch_cfg<F32_256_2x4>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
