@@ -180,6 +180,23 @@ def test_trivial_occupations_and_idempotent_input():
     assert r.status == sp2.OK and r.n == 0 and r.v == [0.0]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_smallest_inputs(prec):
+    """N = 1 admits only n_occ = 0 or 1, where D is 0 or 1 with no square
+    computed; N = 0 is rejected as an invalid argument."""
+    import torch
+    import paper_1507_02087_amd as sp2
+    F = torch.tensor([[0.3]], dtype=torch.float64, device="cuda")
+    for n_occ, d in ((0, 0.0), (1, 1.0)):
+        r = sp2.run_dense(F, -1.0, 1.0, n_occ, precision=prec)
+        assert r.status == sp2.OK and r.n == 0 and r.n_squares == 0
+        assert r.D.shape == (1, 1) and float(r.D[0, 0]) == d
+    with pytest.raises(sp2.SP2Error) as e:
+        sp2.run_dense(torch.zeros((0, 0), dtype=torch.float64, device="cuda"),
+                      -1.0, 1.0, 0, precision=prec)
+    assert e.value.status == sp2.INVALID_ARG
+
+
 def test_invalid_arguments_raise():
     import torch
     import paper_1507_02087_amd as sp2
