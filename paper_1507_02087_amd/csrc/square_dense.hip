@@ -291,6 +291,11 @@ struct CfgF64 {
   static constexpr int MB = TM / 16, NB = TN / 16;
   static constexpr int KS = BK / 4;     // MFMA substeps per K slice
   static constexpr int LDK = BK + 2;    // LDS row stride (doubles)
+  // the main loop's two double-buffered operand arrays and the epilogue's
+  // band share one LDS allocation
+  static constexpr int MAIN_BYTES = 2 * 2 * BM * LDK * 8;
+  static constexpr int EPI_BYTES = TM * (BM + 1) * 8;
+  static constexpr int SMEM = MAIN_BYTES > EPI_BYTES ? MAIN_BYTES : EPI_BYTES;
   struct Acc {
     doublex4 c[MB][NB];
   };
@@ -312,10 +317,11 @@ __device__ __forceinline__ void acc_zero(typename C::Acc& acc) {
 template <class C>
 __device__ __forceinline__ void mainloop_f64(const StepCtx<double>& sc,
                                              const WorkItem& w,
-                                             typename C::Acc& acc) {
+                                             typename C::Acc& acc,
+                                             char* smem) {
   using T = double;
-  __shared__ __attribute__((aligned(16))) T As[2][C::BM][C::LDK];
-  __shared__ __attribute__((aligned(16))) T Bs[2][C::BM][C::LDK];
+  T(*As)[C::BM][C::LDK] = reinterpret_cast<T(*)[C::BM][C::LDK]>(smem);
+  T(*Bs)[C::BM][C::LDK] = As + 2;
   const int2 tt = sc.tile;
   const int ld = sc.ld;
   const T* X = sc.X;
@@ -370,44 +376,6 @@ __device__ __forceinline__ void mainloop_f64(const StepCtx<double>& sc,
   }
 }
 
-template <class C, int MODE>
-__device__ __forceinline__ void epilogue_f64(const StepCtx<double>& sc,
-                                             double* part, int slot,
-                                             const typename C::Acc& acc) {
-  using T = double;
-  const int2 tt = sc.tile;
-  const T* X = sc.X;
-  T* Y = sc.Y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
-  Sums sums;
-  // 16 x 16 fragments: block (m / 2, n / 2) of the wave's region is made of
-  // fragments m, m + 1 and n, n + 1
-  static_assert(C::TM % kMixedBlock == 0 && C::TN % kMixedBlock == 0, "blocks");
-  double bs[C::MB / 2][C::NB / 2] = {};
-#pragma unroll
-  for (int m = 0; m < C::MB; ++m)
-#pragma unroll
-    for (int n = 0; n < C::NB; ++n)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        bs[m / 2][n / 2] += epilogue_at<T, MODE>(
-            X, sc.Sr, Y, sc.ld, sc.n, tt.x, tt.y, C::BM,
-            wm + m * 16 + (lane >> 4) + 4 * j, wn + n * 16 + (lane & 15),
-            acc.c[m][n][j], sc.k, sc.tau, sums);
-  if (sc.blk) {
-#pragma unroll
-    for (int a = 0; a < C::MB / 2; ++a)
-#pragma unroll
-      for (int b = 0; b < C::NB / 2; ++b) {
-        const double t = full_wave_sum(bs[a][b]);
-        const int rb = (tt.x * C::BM + wm) / kMixedBlock + a;
-        const int cb = (tt.y * C::BM + wn) / kMixedBlock + b;
-        if (lane == 0 && rb <= cb) blk_write(sc.blk, sc.nbk, rb, cb, t);
-      }
-  }
-  store_partials<C::THREADS>(sums, part, slot, MODE);
-}
 
 // ============================================================== FP32
 // v_mfma_f32_32x32x2_f32: lane l supplies A[row = l % 32][kk = l / 32] and
@@ -893,8 +861,25 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   if (kt < k1) step(kt, s0);
 }
 
+// Tile-relative position of accumulator register j of fragment (m, n) held
+// by `lane`: the 16 x 16 FP64 layout, or the 32 x 32 layout of the FP32 and
+// BF16 MFMAs.
+template <class C>
+__device__ __forceinline__ void acc_pos(int m, int n, int j, int lane, int& r,
+                                        int& c) {
+  const int wave = threadIdx.x >> 6;
+  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
+  if (sizeof(typename C::T) == 8) {
+    r = wm + m * 16 + (lane >> 4) + 4 * j;
+    c = wn + n * 16 + (lane & 15);
+  } else {
+    r = wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+    c = wn + n * 32 + (lane & 31);
+  }
+}
+
 // Stores the BF16x3 split of four consecutive values (8-byte stores,
-// non-temporal: see epilogue_lds_f32).
+// non-temporal: see epilogue_lds).
 __device__ __forceinline__ void store_split4(__bf16* Yh, __bf16* Yl, size_t i,
                                              floatx4 x) {
   bf16x4 hi, lo;
@@ -909,27 +894,40 @@ __device__ __forceinline__ double octet_sum(double x) {
   return x;
 }
 
-// Epilogue staged through LDS, for an accumulator of the FP32 32x32 layout
-// (register j of lane l: row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32).
-// The tile is processed one band of TM rows at a time (the rows of one row
-// of waves): the waves of the band write their accumulators to LDS, then
-// every thread applies the element epilogue to runs of four consecutive
-// elements of a row (16-byte loads of the old iterate, 16-byte FP32 and
-// 8-byte bf16 stores, whole rows per group of threads) and writes runs of
-// four consecutive elements of the transposed band, read down the columns
-// of LDS. With a row stride of BM + 1 words the column reads put at most
-// two lanes of a wave on one bank and the row reads (lanes four words
-// apart) four; the epilogue's LDS traffic is small beside its stores.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  using type = floatx4;
+};
+template <>
+struct Vec4<double> {
+  using type = doublex4;
+};
+
+// Epilogue staged through LDS, for the accumulators of any family (FP64
+// 16x16 or FP32 32x32 MFMA layout, placed by acc_pos). The tile is
+// processed one band of TM rows at a time (the rows of one row of waves):
+// the waves of the band write their accumulators to LDS, then every thread
+// applies the element epilogue to runs of four consecutive elements of a
+// row (vector loads of the old iterate and vector stores of the new one,
+// with 8-byte stores of the bf16 split in FP32 runs; whole rows per group
+// of threads) and writes runs of four consecutive elements of the
+// transposed band, read down the columns of LDS. With a row stride of
+// BM + 1 elements the column reads put at most two lanes of a wave on one
+// bank and the row reads (lanes four elements apart) four; the epilogue's
+// LDS traffic is small beside its stores.
 // The old iterate is read and the new one written with non-temporal hints:
 // neither is touched again before the next square, and keeping them out of
 // L2 leaves it to the operand panels that the other workgroups stream
 // (1.3 % faster squares at N = 8192).
 template <class C, int MODE>
-__device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
-                                                 double* part, int slot,
-                                                 const typename C::Acc& acc,
-                                                 char* smem) {
-  using T = float;
+__device__ __forceinline__ void epilogue_lds(const StepCtx<typename C::T>& sc,
+                                             double* part, int slot,
+                                             const typename C::Acc& acc,
+                                             char* smem) {
+  using T = typename C::T;
+  using V4 = typename Vec4<T>::type;
   constexpr int BM = C::BM, TM = C::TM, LD = BM + 1;
   constexpr int V = 4;                   // consecutive elements per thread
   constexpr int TPR = BM / V;            // threads per row of the tile
@@ -946,8 +944,8 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
   const bool diag = (I == J);
   const int ld = sc.ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wg = wave / C::WN, wn = (wave % C::WN) * C::TN;
-  const bool split = (sc.Yh != nullptr);
+  const int wg = wave / C::WN;
+  const bool split = (sizeof(T) == 4) && (sc.Yh != nullptr);
   Sums sums;
   // Thread tid owns columns c0 .. c0 + 3 (c0 = 4 (tid % TPR)) of the rows
   // ph + R j of a band (ph = tid / TPR). Rows are visited one 32-row block at
@@ -957,32 +955,37 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
   // processed, and a band's first batch before its accumulators go to LDS.
   const int c0 = (tid % TPR) * V, ph = tid / TPR;
   const int gc0 = J * BM + c0;
-  constexpr int NB = (MODE == 2) ? (NJ < 2 ? NJ : 2) : NJ;
+  // rows per load batch: all of a block row's (two in the McWeeny product
+  // mode), halved where a band would otherwise hold an odd number of
+  // batches (the loop below processes them in pairs)
+  constexpr int NB0 = (MODE == 2) ? (NJ < 2 ? NJ : 2) : NJ;
+  constexpr int NB = ((TM / kMixedBlock) * (NJ / NB0)) % 2 == 0 || NB0 < 2
+                         ? NB0 : NB0 / 2;
   constexpr int PER_RB = NJ / NB;
   constexpr int NBATCH = (TM / kMixedBlock) * PER_RB;
   static_assert(NJ % NB == 0 && NBATCH % 2 == 0, "load batches");
-  floatx4 xa[NB], sa[NB], xb[NB], sb[NB];
+  V4 xa[NB], sa[NB], xb[NB], sb[NB];
   // in a diagonal tile, rows whose four elements all lie below the diagonal
   // are neither loaded nor processed
-  auto load_batch = [&](int r0, int bi, floatx4* xv, floatx4* sv) {
+  auto load_batch = [&](int r0, int bi, V4* xv, V4* sv) {
     const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
       const int gr = r0 + rb * kMixedBlock + ph + R * (j0 + jj);
       const size_t idx = static_cast<size_t>(gr) * ld + gc0;
       const bool any = !(diag && gr > gc0 + V - 1);
-      const floatx4 z = {0.f, 0.f, 0.f, 0.f};
+      const V4 z = {T(0), T(0), T(0), T(0)};
       xv[jj] = any ? __builtin_nontemporal_load(
-                         gro(reinterpret_cast<const floatx4*>(sc.X + idx)))
+                         gro(reinterpret_cast<const V4*>(sc.X + idx)))
                    : z;
       sv[jj] = (MODE == 2 && any)
                    ? __builtin_nontemporal_load(
-                         gro(reinterpret_cast<const floatx4*>(sc.Sr + idx)))
+                         gro(reinterpret_cast<const V4*>(sc.Sr + idx)))
                    : z;
     }
   };
   double bs = 0.0;
-  auto process = [&](int r0, int bi, const floatx4* xv, const floatx4* sv) {
+  auto process = [&](int r0, int bi, const V4* xv, const V4* sv) {
     const int rb = bi / PER_RB, j0 = (bi % PER_RB) * NB;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
@@ -990,7 +993,7 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
       const int gr = r0 + rr;
       const size_t idx = static_cast<size_t>(gr) * ld + gc0;
       if (diag && gr > gc0 + V - 1) continue;
-      floatx4 xn4;
+      V4 xn4;
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         const int gc = gc0 + i;
@@ -1007,15 +1010,16 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
         }
       }
       if (!diag || gr <= gc0) {   // all four elements are processed
-        __builtin_nontemporal_store(
-            xn4, grw(reinterpret_cast<floatx4*>(sc.Y + idx)));
-        if (split) store_split4(sc.Yh, sc.Yl, idx, xn4);
+        __builtin_nontemporal_store(xn4, grw(reinterpret_cast<V4*>(sc.Y + idx)));
+        if constexpr (sizeof(T) == 4)
+          if (split) store_split4(sc.Yh, sc.Yl, idx, xn4);
       } else {                    // the run crosses the diagonal
 #pragma unroll
         for (int i = 0; i < V; ++i)
           if (gr <= gc0 + i) {
             *grw(sc.Y + idx + i) = xn4[i];
-            if (split) store_split(sc.Yh, sc.Yl, idx + i, xn4[i]);
+            if constexpr (sizeof(T) == 4)
+              if (split) store_split(sc.Yh, sc.Yl, idx + i, xn4[i]);
           }
       }
     }
@@ -1039,15 +1043,16 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
     load_batch(r0, 0, xa, sa);
     __syncthreads();
     if (wg == g) {
+      constexpr int PER = sizeof(acc.c[0][0]) / sizeof(T);
 #pragma unroll
       for (int m = 0; m < C::MB; ++m)
 #pragma unroll
         for (int n = 0; n < C::NB; ++n)
 #pragma unroll
-          for (int j = 0; j < 16; ++j) {
-            const int rr = m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-            const int cc = wn + n * 32 + (lane & 31);
-            S[rr * LD + cc] = acc.c[m][n][j];
+          for (int j = 0; j < PER; ++j) {
+            int rr, cc;
+            acc_pos<C>(m, n, j, lane, rr, cc);
+            S[(rr - g * TM) * LD + cc] = acc.c[m][n][j];
           }
     }
     __syncthreads();
@@ -1069,21 +1074,22 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
     for (int oc = tid / TPO; oc < BM; oc += OPP) {
       const int gc = J * BM + oc;
       if (diag && gr0 >= gc) continue;   // all four on or below the diagonal
-      floatx4 v;
+      V4 v;
 #pragma unroll
       for (int i = 0; i < V; ++i) v[i] = S[(r4 + i) * LD + oc];
       const size_t idt = static_cast<size_t>(gc) * ld + gr0;
       if (!diag || gr0 + V - 1 < gc) {
         if (sc.mirror32)
-          __builtin_nontemporal_store(
-              v, grw(reinterpret_cast<floatx4*>(sc.Y + idt)));
-        if (split) store_split4(sc.Yh, sc.Yl, idt, v);
+          __builtin_nontemporal_store(v, grw(reinterpret_cast<V4*>(sc.Y + idt)));
+        if constexpr (sizeof(T) == 4)
+          if (split) store_split4(sc.Yh, sc.Yl, idt, v);
       } else {
 #pragma unroll
         for (int i = 0; i < V; ++i)
           if (gr0 + i < gc) {
             if (sc.mirror32) *grw(sc.Y + idt + i) = v[i];
-            if (split) store_split(sc.Yh, sc.Yl, idt + i, v[i]);
+            if constexpr (sizeof(T) == 4)
+              if (split) store_split(sc.Yh, sc.Yl, idt + i, v[i]);
           }
       }
     }
@@ -1092,23 +1098,6 @@ __device__ __forceinline__ void epilogue_lds_f32(const StepCtx<float>& sc,
 }
 
 // ============================================================== drivers
-// Tile-relative position of accumulator register j of fragment (m, n) held
-// by `lane`: the 16 x 16 FP64 layout, or the 32 x 32 layout of the FP32 and
-// BF16 MFMAs.
-template <class C>
-__device__ __forceinline__ void acc_pos(int m, int n, int j, int lane, int& r,
-                                        int& c) {
-  const int wave = threadIdx.x >> 6;
-  const int wm = (wave / C::WN) * C::TM, wn = (wave % C::WN) * C::TN;
-  if (sizeof(typename C::T) == 8) {
-    r = wm + m * 16 + (lane >> 4) + 4 * j;
-    c = wn + n * 16 + (lane & 15);
-  } else {
-    r = wm + m * 32 + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
-    c = wn + n * 32 + (lane & 31);
-  }
-}
-
 // A K-range piece of a tail tile is stored row-major (BM x BM), so that the
 // tail reduction can work on bands of rows; a register index is a row
 // segment of 16 or 32 consecutive values across the lanes (coalesced).
@@ -1135,16 +1124,16 @@ struct Ops;
 template <int A, int B, int Cc, int D>
 struct Ops<CfgF64<A, B, Cc, D>> {
   using C = CfgF64<A, B, Cc, D>;
-  static constexpr int kSmem = 16;   // the main loop declares its own LDS
+  static constexpr int kSmem = C::SMEM;
   using T = typename C::T;
   __device__ static void main(const StepCtx<T>& sc, const WorkItem& w,
-                              typename C::Acc& acc, char*) {
-    mainloop_f64<C>(sc, w, acc);
+                              typename C::Acc& acc, char* smem) {
+    mainloop_f64<C>(sc, w, acc, smem);
   }
   template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
-                             const typename C::Acc& acc, char*) {
-    epilogue_f64<C, MODE>(sc, part, slot, acc);
+                             const typename C::Acc& acc, char* smem) {
+    epilogue_lds<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
@@ -1160,7 +1149,7 @@ struct Ops<CfgF32<A, B, Cc, D>> {
   template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
+    epilogue_lds<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
@@ -1193,7 +1182,7 @@ struct Ops<CfgB3S<A, B, Cc, D>> {
   template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
+    epilogue_lds<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
@@ -1209,7 +1198,7 @@ struct Ops<CfgB3P<A, B, Cc, D>> {
   template <int MODE>
   __device__ static void epi(const StepCtx<T>& sc, double* part, int slot,
                              const typename C::Acc& acc, char* smem) {
-    epilogue_lds_f32<C, MODE>(sc, part, slot, acc, smem);
+    epilogue_lds<C, MODE>(sc, part, slot, acc, smem);
   }
 };
 
