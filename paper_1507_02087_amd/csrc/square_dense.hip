@@ -1202,8 +1202,23 @@ struct Ops<CfgB3P<A, B, Cc, D>> {
   }
 };
 
+// Waves per SIMD a configuration is compiled for (the register budget
+// follows from it; HIP's second launch bound): 4 for the 128-tile FP64
+// configuration with 2 x 4 waves, i.e. two workgroups per CU, whose LDS (two
+// operand buffers of 36 KiB) leaves room for a second workgroup to run while
+// the first waits at a slice barrier; 1 (no constraint) for the others.
+template <class C>
+struct MinWaves {
+  static constexpr int value = 1;
+};
+template <>
+struct MinWaves<CfgF64<128, 2, 4, 16>> {
+  static constexpr int value = 4;
+};
+
 template <class C, int MODE>
-__global__ __launch_bounds__(C::THREADS) void square_kernel(SquareArgs a) {
+__global__ __launch_bounds__(C::THREADS, MinWaves<C>::value) void square_kernel(
+    SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
   const WorkItem w = a.items[blockIdx.x];
   if (w.slot < 0) return;
@@ -1425,7 +1440,7 @@ constexpr KernelConfig describe(int precision, int occupancy,
 // Occupancy = workgroups per CU that the configuration's LDS and registers
 // allow; the host uses it to size the split of tail tiles.
 const KernelConfig kConfigs[] = {
-    SP2_DESCRIBE(F64_128_2x4, 0, 1), SP2_DESCRIBE(F64_128_2x2, 0, 1),
+    SP2_DESCRIBE(F64_128_2x4, 0, 2), SP2_DESCRIBE(F64_128_2x2, 0, 1),
     SP2_DESCRIBE(F64_64_2x2, 0, 2),  SP2_DESCRIBE(F32_128_2x2, 1, 2),
     SP2_DESCRIBE(F32_128_2x4, 1, 1), SP2_DESCRIBE(F32_256_2x2, 1, 1),
     SP2_DESCRIBE(B3_128_2x2, 2, 1),  SP2_DESCRIBE(B3_256_2x2, 2, 1),
