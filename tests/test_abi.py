@@ -71,6 +71,28 @@ def test_default_options_and_kernel_configs():
     assert lib.sp2_kernel_config_info(len(cfgs) + 1, None, None, None, None, None) == sp2.INVALID_ARG
 
 
+def test_shipped_kernel_table_is_consistent():
+    """Every entry of the autotuned table names a configuration the library
+    has, of the entry's precision; per precision the size limits rise and
+    reach the largest size the tuner covers, so no size falls through to the
+    built-in default by accident."""
+    import json
+    import paper_1507_02087_amd as sp2
+    sp2.load_library()
+    cfgs = {c["name"]: c for c in sp2.kernel_configs()}
+    with open(sp2.TABLE_PATH) as fh:
+        entries = json.load(fh)["entries"]
+    assert entries
+    last = {}
+    for e in entries:
+        assert e["name"] in cfgs, e
+        assert cfgs[e["name"]]["precision"] == e["precision"], e
+        assert e["n_max"] > last.get(e["precision"], 0), e
+        last[e["precision"]] = e["n_max"]
+    assert set(last) == {"fp64", "fp32", "bf16x3"}
+    assert min(last.values()) >= 8192
+
+
 def test_library_shares_torch_hip_runtime():
     """libsp2.so and torch must use one HIP runtime: after loading through
     the binding, exactly one libamdhip64 is mapped in the process."""
