@@ -775,23 +775,25 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   struct Frag {
     bf16x8 ah[C::MB], al[C::MB], bh[C::NB], bl[C::NB];
   };
+  // Issue order follows the first MFMAs' needs: ah[0] and the bh row of
+  // fragments first, so that the first product of a k step waits for two
+  // reads instead of the whole A panel; then the rest of ah, bl and al.
   auto fread = [&](Frag& f, int b, int s8) {
+    auto oa = [&](int m) { return swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8); };
+    auto ob = [&](int n) { return swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8); };
+    f.ah[0] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + oa(0));
 #pragma unroll
-    for (int m = 0; m < C::MB; ++m) {
-      const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
-      f.ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + o);
-    }
+    for (int n = 0; n < C::NB; ++n)
+      f.bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + ob(n));
 #pragma unroll
-    for (int n = 0; n < C::NB; ++n) {
-      const int o = swz_off<C::BK>(wn + n * 32 + r, h * C::KH + s8);
-      f.bh[n] = *reinterpret_cast<const bf16x8*>(arr(b, 2) + o);
-      f.bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + o);
-    }
+    for (int m = 1; m < C::MB; ++m)
+      f.ah[m] = *reinterpret_cast<const bf16x8*>(arr(b, 0) + oa(m));
 #pragma unroll
-    for (int m = 0; m < C::MB; ++m) {
-      const int o = swz_off<C::BK>(wm + m * 32 + r, h * C::KH + s8);
-      f.al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + o);
-    }
+    for (int n = 0; n < C::NB; ++n)
+      f.bl[n] = *reinterpret_cast<const bf16x8*>(arr(b, 3) + ob(n));
+#pragma unroll
+    for (int m = 0; m < C::MB; ++m)
+      f.al[m] = *reinterpret_cast<const bf16x8*>(arr(b, 1) + oa(m));
   };
   auto mma = [&](const Frag& f) {
 #pragma unroll
