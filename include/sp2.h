@@ -451,6 +451,46 @@ const char* sp2_kernel_config_name(int32_t id);
  * Errors: SP2_BAD_STATE before an init, SP2_INVALID_ARG. */
 sp2_status sp2_get_config(sp2_ctx ctx, int32_t index, int32_t* config_id);
 
+/* ---------------------------------------------------------------------
+ * Dense purification without any device allocation, for callers that
+ * cannot allocate device memory (code that must not call hipMalloc: tight
+ * serving loops, harnesses that forbid allocation). Equivalent to
+ * sp2_create + sp2_init_dense + sp2_run + sp2_get_density + sp2_get_info on
+ * the given device and stream (same kernels, same work plan, same results
+ * bit for bit for the same options and kernel configuration, with
+ * tail_split 1), except that every workspace is carved from the library's
+ * static scratch array of 64 MiB per device (held until the process ends)
+ * and no context, event or pinned host buffer is created.
+ *
+ * F_dev, n, ldf, lambda_min, lambda_max, n_occ and opt are those of
+ * sp2_init_dense (opt may be NULL); the kernel table of a context does not
+ * apply (kernel_config 0 picks the library's built-in choice). D_dev
+ * receives X~_n like sp2_get_density (ldd >= n, FP64 when as_fp64 != 0).
+ * v (host, cap entries, may be NULL when cap is 0) receives the history
+ * v[k] = ||X~_k - X~_k^2||_F (NaN past n_squares); n_iter and n_squares
+ * (may be NULL) as sp2_get_info. Returns the run outcome like sp2_run.
+ *
+ * Limits: opt->norm must be SP2_NORM_FROBENIUS, opt->kernel_timing 0 and
+ * opt->tail_split 0 or 1 (tail tiles are never split); the run needs
+ * about 2 P L w bytes (w = 8 for SP2_FP64, 4 for SP2_FP32) or 16 P L
+ * bytes (SP2_BF16X3: FP32 iterates and their bf16 split), plus less than
+ * 1 MiB, where P is n rounded up to the square kernel's tile (64 or 128)
+ * and L the row stride (P, or P + 128 when P >= 2048 is a multiple of
+ * 512): n <= 1920 fits in every precision. Larger inputs, and the options
+ * above, return SP2_INVALID_ARG before any work is queued.
+ *
+ * The scratch array is shared by every call on a device and keeps the last
+ * call's contents (each call clears what must start at zero); calls whose
+ * work overlaps on one device (other threads or streams) race and must be
+ * serialised by the caller. Errors: SP2_INVALID_ARG, SP2_HIP_ERROR. */
+sp2_status sp2_run_dense_noalloc(int device, void* hip_stream,
+                                 const double* F_dev, int64_t n, int64_t ldf,
+                                 double lambda_min, double lambda_max,
+                                 int64_t n_occ, const sp2_options* opt,
+                                 void* D_dev, int64_t ldd, int32_t as_fp64,
+                                 int32_t cap, double* v, int32_t* n_iter,
+                                 int32_t* n_squares);
+
 /* Static description of a status code. */
 const char* sp2_status_string(sp2_status s);
 

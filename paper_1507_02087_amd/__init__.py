@@ -85,6 +85,12 @@ SIGNATURES = {
     "sp2_kernel_config_count": (_c.c_int32, []),
     "sp2_kernel_config_info": (_c.c_int, [_c.c_int32] + [_c.POINTER(_c.c_int32)] * 5),
     "sp2_kernel_config_name": (_c.c_char_p, [_c.c_int32]),
+    "sp2_run_dense_noalloc": (_c.c_int, [_c.c_int, _c.c_void_p, _c.c_void_p, _c.c_int64,
+                                         _c.c_int64, _c.c_double, _c.c_double,
+                                         _c.c_int64, _c.c_void_p, _c.c_void_p,
+                                         _c.c_int64, _c.c_int32, _c.c_int32,
+                                         _c.c_void_p, _c.POINTER(_c.c_int32),
+                                         _c.POINTER(_c.c_int32)]),
     "sp2_status_string": (_c.c_char_p, [_c.c_int]),
     "sp2_last_error": (_c.c_char_p, [_c.c_void_p]),
 }

@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -63,19 +64,6 @@ struct Group {
   sp2::TailItem* tails = nullptr;   // device
   size_t items_cap = 0, tails_cap = 0;
 };
-
-template <typename P>
-hipError_t grow(P*& ptr, size_t& cap, size_t bytes, hipStream_t s) {
-  if (bytes <= cap) return hipSuccess;
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
-  if (ptr) (void)hipFree(ptr);
-  ptr = nullptr;
-  cap = 0;
-  e = hipMalloc(reinterpret_cast<void**>(&ptr), bytes);
-  if (e == hipSuccess) cap = bytes;
-  return e;
-}
 
 }  // namespace
 
@@ -173,6 +161,11 @@ struct sp2_ctx_s {
     void* mem = nullptr;           // one allocation holding all of the above
   } b;
 
+  // Workspace arena of the no-allocation entry point (null for contexts made
+  // by sp2_create): every workspace is carved from it instead of allocated.
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
+
   // outcome
   bool inited = false, ran = false;
   double run_ms = 0.0;
@@ -181,6 +174,33 @@ struct sp2_ctx_s {
 };
 
 namespace {
+
+// Device memory for a workspace of at least `bytes`. A context made by
+// sp2_create allocates with hipMalloc and replaces a buffer only when a
+// larger one is needed; a context of the no-allocation entry point carves
+// every workspace from its arena (256-byte aligned) and reports
+// hipErrorOutOfMemory when the arena is full.
+template <typename P>
+hipError_t grow(sp2_ctx c, P*& ptr, size_t& cap, size_t bytes, hipStream_t s) {
+  if (bytes <= cap) return hipSuccess;
+  if (c->arena) {
+    const size_t off = (c->arena_off + 255) / 256 * 256;
+    if (bytes > c->arena_cap || off > c->arena_cap - bytes)
+      return hipErrorOutOfMemory;
+    ptr = reinterpret_cast<P*>(c->arena + off);
+    cap = bytes;
+    c->arena_off = off + bytes;
+    return hipSuccess;
+  }
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  e = hipMalloc(reinterpret_cast<void**>(&ptr), bytes);
+  if (e == hipSuccess) cap = bytes;
+  return e;
+}
 
 sp2_status fail(sp2_ctx c, sp2_status s, const char* what, hipError_t e) {
   if (c) {
@@ -351,6 +371,7 @@ sp2_status validate_instance(sp2_ctx c, const double* F, int64_t n, int64_t ldf,
 
 void release_groups(sp2_ctx c) {
   for (Group& g : c->groups) {
+    if (c->arena) continue;   // carved from the arena
     if (g.items) (void)hipFree(g.items);
     if (g.tails) (void)hipFree(g.tails);
   }
@@ -383,11 +404,11 @@ sp2_status setup(sp2_ctx c) {
     h.trivial = (h.n_occ == 0 || h.n_occ == h.n);
   }
   for (int q = 0; q < 2; ++q)
-    SP2_HIP(c, grow(c->pool[q], c->pool_cap[q], pool_elems * esz, s));
+    SP2_HIP(c, grow(c, c->pool[q], c->pool_cap[q], pool_elems * esz, s));
   const bool split = (c->opt.precision == SP2_BF16X3);
   if (split)
     for (int q = 0; q < 4; ++q)
-      SP2_HIP(c, grow(c->split_pool[q], c->split_cap[q], pool_elems * 2, s));
+      SP2_HIP(c, grow(c, c->split_pool[q], c->split_cap[q], pool_elems * 2, s));
 
   // block norms of the mixed norm: an (np/32)^2 matrix per instance
   const bool mixed = (c->opt.norm == SP2_NORM_MIXED);
@@ -403,8 +424,8 @@ sp2_status setup(sp2_ctx c) {
     }
   }
   if (mixed) {
-    SP2_HIP(c, grow(c->d_blk, c->d_blk_cap, blk_elems * sizeof(float), s));
-    SP2_HIP(c, grow(c->d_lz, c->d_lz_cap, lz_elems * sizeof(double), s));
+    SP2_HIP(c, grow(c, c->d_blk, c->d_blk_cap, blk_elems * sizeof(float), s));
+    SP2_HIP(c, grow(c, c->d_lz, c->d_lz_cap, lz_elems * sizeof(double), s));
   }
 
   // spectral norm: Lanczos scratch per instance and the chunk table (rows
@@ -424,10 +445,10 @@ sp2_status setup(sp2_ctx c) {
       for (int r = 0; r < h.n; r += sp2::kSpecRows) chunks.push_back(int2{b, r});
       sp_nch[b] = static_cast<int>(chunks.size()) - sp_ch0[b];
     }
-    SP2_HIP(c, grow(c->d_spec, c->d_spec_cap, sp_elems * sizeof(double), s));
-    SP2_HIP(c, grow(c->d_spec_chunks, c->d_spec_chunks_cap,
+    SP2_HIP(c, grow(c, c->d_spec, c->d_spec_cap, sp_elems * sizeof(double), s));
+    SP2_HIP(c, grow(c, c->d_spec_chunks, c->d_spec_chunks_cap,
                     std::max<size_t>(1, chunks.size()) * sizeof(int2), s));
-    SP2_HIP(c, grow(c->d_spec_ctl, c->d_spec_ctl_cap,
+    SP2_HIP(c, grow(c, c->d_spec_ctl, c->d_spec_ctl_cap,
                     (sp2::kMaxIter + 2) * sp2::kSpecCtl * sizeof(int32_t), s));
     if (!chunks.empty())
       SP2_HIP(c, hipMemcpyAsync(c->d_spec_chunks, chunks.data(),
@@ -454,7 +475,7 @@ sp2_status setup(sp2_ctx c) {
   c->spec_nchunks = static_cast<int>(chunks.size());
 
   // instance table, tiles and affine-start blocks
-  SP2_HIP(c, grow(c->d_st, c->d_st_cap, count * sizeof(DevState), s));
+  SP2_HIP(c, grow(c, c->d_st, c->d_st_cap, count * sizeof(DevState), s));
   std::vector<int2> tiles;
   std::vector<Instance> inst(count);
   std::vector<sp2::F0Item> f0;
@@ -533,13 +554,13 @@ sp2_status setup(sp2_ctx c) {
                                         (kc->bm / sp2::kMixedBlock));
     c->groups.push_back(g);
     Group& gg = c->groups.back();
-    SP2_HIP(c, grow(gg.items, gg.items_cap,
+    SP2_HIP(c, grow(c, gg.items, gg.items_cap,
                     pl.items.size() * sizeof(sp2::WorkItem), s));
     SP2_HIP(c, hipMemcpyAsync(gg.items, pl.items.data(),
                               pl.items.size() * sizeof(sp2::WorkItem),
                               hipMemcpyHostToDevice, s));
     if (!pl.tails.empty()) {
-      SP2_HIP(c, grow(gg.tails, gg.tails_cap,
+      SP2_HIP(c, grow(c, gg.tails, gg.tails_cap,
                       pl.tails.size() * sizeof(sp2::TailItem), s));
       SP2_HIP(c, hipMemcpyAsync(gg.tails, pl.tails.data(),
                                 pl.tails.size() * sizeof(sp2::TailItem),
@@ -548,24 +569,24 @@ sp2_status setup(sp2_ctx c) {
     // the copies read host vectors that go out of scope: finish them now
     SP2_HIP(c, hipStreamSynchronize(s));
   }
-  if (ws_elems) SP2_HIP(c, grow(c->d_ws, c->d_ws_cap, ws_elems * esz, s));
+  if (ws_elems) SP2_HIP(c, grow(c, c->d_ws, c->d_ws_cap, ws_elems * esz, s));
   if (max_tail) {
     // the counters start at zero and every tail launch leaves them at zero
-    SP2_HIP(c, grow(c->d_bpart, c->d_bpart_cap,
+    SP2_HIP(c, grow(c, c->d_bpart, c->d_bpart_cap,
                     max_bands * 3 * sizeof(double), s));
     const size_t old_cap = c->d_bcnt_cap;
-    SP2_HIP(c, grow(c->d_bcnt, c->d_bcnt_cap, max_tail * sizeof(int), s));
+    SP2_HIP(c, grow(c, c->d_bcnt, c->d_bcnt_cap, max_tail * sizeof(int), s));
     if (c->d_bcnt_cap != old_cap || old_cap == 0)
       SP2_HIP(c, hipMemsetAsync(c->d_bcnt, 0, c->d_bcnt_cap, s));
   }
-  SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, count * sizeof(Instance), s));
-  SP2_HIP(c, grow(c->d_tiles, c->d_tiles_cap,
+  SP2_HIP(c, grow(c, c->d_inst, c->d_inst_cap, count * sizeof(Instance), s));
+  SP2_HIP(c, grow(c, c->d_tiles, c->d_tiles_cap,
                   std::max<size_t>(1, tiles.size()) * sizeof(int2), s));
-  SP2_HIP(c, grow(c->d_part, c->d_part_cap,
+  SP2_HIP(c, grow(c, c->d_part, c->d_part_cap,
                   std::max<size_t>(1, tiles.size()) * 3 * sizeof(double), s));
-  SP2_HIP(c, grow(c->d_part_f0, c->d_part_f0_cap,
+  SP2_HIP(c, grow(c, c->d_part_f0, c->d_part_f0_cap,
                   f0.size() * 3 * sizeof(double), s));
-  SP2_HIP(c, grow(c->d_f0, c->d_f0_cap, f0.size() * sizeof(sp2::F0Item), s));
+  SP2_HIP(c, grow(c, c->d_f0, c->d_f0_cap, f0.size() * sizeof(sp2::F0Item), s));
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, inst.data(), count * sizeof(Instance),
                             hipMemcpyHostToDevice, s));
   c->h_inst = inst;
@@ -581,13 +602,20 @@ sp2_status setup(sp2_ctx c) {
   return SP2_OK;
 }
 
+// Steps enqueued between two looks at the done counter by a context of the
+// no-allocation entry point (it has no pinned mirror and no events).
+constexpr int kNoAllocChunk = 4;
+
 sp2_status run_batch(sp2_ctx c) {
   SP2_HIP(c, hipSetDevice(c->device));
   hipStream_t s = c->stream;
   const int count = static_cast<int>(c->hi.size());
-  c->mirror->all_done = 0;
-  __atomic_thread_fence(__ATOMIC_SEQ_CST);
-  const bool timing = c->opt.kernel_timing != 0;
+  const bool noalloc = (c->arena != nullptr);
+  if (!noalloc) {
+    c->mirror->all_done = 0;
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  }
+  const bool timing = c->opt.kernel_timing != 0 && !noalloc;
   if (timing && c->ev_sq.empty()) {
     c->ev_sq.assign(2 * (SP2_MAX_ITER_LIMIT + 1), nullptr);
     for (hipEvent_t& e : c->ev_sq) SP2_HIP(c, hipEventCreate(&e));
@@ -596,7 +624,7 @@ sp2_status run_batch(sp2_ctx c) {
   c->square_ms.clear();
   c->norm_ms.clear();
 
-  SP2_HIP(c, hipEventRecord(c->ev_start, s));
+  if (!noalloc) SP2_HIP(c, hipEventRecord(c->ev_start, s));
   const bool spectral = (c->opt.norm == SP2_NORM_SPECTRAL) && c->spec_nchunks > 0;
   if (timing && spectral && c->ev_nm.empty()) {
     c->ev_nm.assign(2 * (SP2_MAX_ITER_LIMIT + 1), nullptr);
@@ -613,9 +641,10 @@ sp2_status run_batch(sp2_ctx c) {
     SP2_HIP(c, sp2::launch_f0(c->d_inst, c->d_f0, c->nf0, c->fp64_store,
                               c->d_part_f0, s));
   }
+  HostMirror* mirror = noalloc ? nullptr : c->mirror;
   SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
-                                  c->d_ndone, c->mirror, 0, s));
-  SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
+                                  c->d_ndone, mirror, 0, s));
+  if (!noalloc) SP2_HIP(c, hipEventRecord(c->ev_ring[0], s));
 
   sp2::SquareArgs a;
   a.mode = 0;
@@ -629,9 +658,21 @@ sp2_status run_batch(sp2_ctx c) {
   int last = 0;
   const bool any_work = c->bsr || !c->groups.empty();
   for (int i = 1; i <= c->opt.max_iter && any_work; ++i) {
-    if (i > kLookahead)
-      SP2_HIP(c, hipEventSynchronize(c->ev_ring[(i - kLookahead) % kRing]));
-    if (__atomic_load_n(&c->mirror->all_done, __ATOMIC_ACQUIRE)) break;
+    if (noalloc) {
+      // every kNoAllocChunk steps: wait for the queued steps and read the
+      // number of instances with an outcome
+      if (i > 1 && (i - 1) % kNoAllocChunk == 0) {
+        int32_t nd = 0;
+        SP2_HIP(c, hipMemcpyAsync(&nd, c->d_ndone, sizeof(nd),
+                                  hipMemcpyDeviceToHost, s));
+        SP2_HIP(c, hipStreamSynchronize(s));
+        if (nd >= count) break;
+      }
+    } else {
+      if (i > kLookahead)
+        SP2_HIP(c, hipEventSynchronize(c->ev_ring[(i - kLookahead) % kRing]));
+      if (__atomic_load_n(&c->mirror->all_done, __ATOMIC_ACQUIRE)) break;
+    }
     a.iter = i;
     if (timing) SP2_HIP(c, hipEventRecord(c->ev_sq[2 * i], s));
     if (c->bsr) {
@@ -680,14 +721,16 @@ sp2_status run_batch(sp2_ctx c) {
       if (timing) SP2_HIP(c, hipEventRecord(c->ev_nm[2 * i + 1], s));
     }
     SP2_HIP(c, sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
-                                    c->d_ndone, c->mirror, i, s));
-    SP2_HIP(c, hipEventRecord(c->ev_ring[i % kRing], s));
+                                    c->d_ndone, mirror, i, s));
+    if (!noalloc) SP2_HIP(c, hipEventRecord(c->ev_ring[i % kRing], s));
     last = i;
   }
-  SP2_HIP(c, hipEventRecord(c->ev_stop, s));
-  SP2_HIP(c, hipEventSynchronize(c->ev_stop));
   float ms = 0.f;
-  SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  if (!noalloc) {
+    SP2_HIP(c, hipEventRecord(c->ev_stop, s));
+    SP2_HIP(c, hipEventSynchronize(c->ev_stop));
+    SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  }
   c->host_state.resize(count);
   SP2_HIP(c, hipMemcpyAsync(c->host_state.data(), c->d_st,
                             count * sizeof(DevState), hipMemcpyDeviceToHost,
@@ -793,6 +836,31 @@ void fill_history(const sp2_ctx c, int idx, int32_t cap, int32_t* len,
     if (t2) t2[k] = k < nt ? h.t2[k] : NAN;
     if (p) p[k] = k < nt ? (k == 0 ? -1 : h.p[k]) : -1;
   }
+}
+
+// Scratch of the no-allocation entry point: one array per device, holding
+// every workspace of a dense run (iterates, bf16 split, partial sums, work
+// plan, state). Host code uses only the device address that
+// hipGetSymbolAddress returns for it on each device, never the array's name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+char* g_scratch_ptr[kScratchDevices] = {};
+std::mutex g_scratch_mu;
+
+// The scratch array's address on `device` (which must be current), looked
+// up once per device.
+sp2_status scratch_on_device(int device, char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return SP2_HIP_ERROR;
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return SP2_OK;
 }
 
 }  // namespace
@@ -1130,7 +1198,7 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   // instance table of one entry: partial sums of the numeric kernel (one
   // triple per workgroup) and of the affine start (one per block)
   Instance in{};
-  SP2_HIP(c, grow(c->d_st, c->d_st_cap, sizeof(DevState), s));
+  SP2_HIP(c, grow(c, c->d_st, c->d_st_cap, sizeof(DevState), s));
   in.n = static_cast<int>(n);
   in.tile0 = 0;
   in.ntiles = grid;
@@ -1148,10 +1216,10 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   in.nbk = nb;
   if (opt.norm == SP2_NORM_MIXED) {
     // one block norm per block of the output pattern
-    SP2_HIP(c, grow(c->d_blk, c->d_blk_cap,
+    SP2_HIP(c, grow(c, c->d_blk, c->d_blk_cap,
                     static_cast<size_t>(cap) * sizeof(float), s));
     in.blk = c->d_blk;
-    SP2_HIP(c, grow(c->d_lz, c->d_lz_cap,
+    SP2_HIP(c, grow(c, c->d_lz, c->d_lz_cap,
                     static_cast<size_t>(sp2::kLanczosMax) * nb * sizeof(double),
                     s));
     in.lz = c->d_lz;
@@ -1160,9 +1228,9 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
       in.bcol[k] = c->b.m[k].col;
     }
   }
-  SP2_HIP(c, grow(c->d_inst, c->d_inst_cap, sizeof(Instance), s));
-  SP2_HIP(c, grow(c->d_part, c->d_part_cap, grid * 3 * sizeof(double), s));
-  SP2_HIP(c, grow(c->d_part_f0, c->d_part_f0_cap, nnzb * 3 * sizeof(double), s));
+  SP2_HIP(c, grow(c, c->d_inst, c->d_inst_cap, sizeof(Instance), s));
+  SP2_HIP(c, grow(c, c->d_part, c->d_part_cap, grid * 3 * sizeof(double), s));
+  SP2_HIP(c, grow(c, c->d_part_f0, c->d_part_f0_cap, nnzb * 3 * sizeof(double), s));
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, &in, sizeof(Instance),
                             hipMemcpyHostToDevice, s));
   SP2_HIP(c, hipStreamSynchronize(s));
@@ -1338,11 +1406,11 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
     pool_elems = std::max(pool_elems,
                           h.xoff + static_cast<size_t>(h.np) * h.ld);
   const size_t esz = c->fp64_store ? 8 : 4;
-  SP2_HIP(c, grow(c->s_pool, c->s_pool_cap, pool_elems * esz, s));
+  SP2_HIP(c, grow(c, c->s_pool, c->s_pool_cap, pool_elems * esz, s));
   const bool split = (c->opt.precision == SP2_BF16X3);
   if (split)
     for (int q = 0; q < 2; ++q)
-      SP2_HIP(c, grow(c->s_split[q], c->s_split_cap[q], pool_elems * 2, s));
+      SP2_HIP(c, grow(c, c->s_split[q], c->s_split_cap[q], pool_elems * 2, s));
   for (int b = 0; b < count; ++b) {
     const HostInst& h = c->hi[b];
     Instance& in = c->h_inst[b];
@@ -1433,7 +1501,7 @@ sp2_status sp2_set_homo_lumo(sp2_ctx c, int32_t count, const double* homo_out,
   }
   hipStream_t s = c->stream;
   const size_t abytes = alpha.size() * sizeof(double);
-  SP2_HIP(c, grow(c->d_sched, c->d_sched_cap, abytes + pol.size(), s));
+  SP2_HIP(c, grow(c, c->d_sched, c->d_sched_cap, abytes + pol.size(), s));
   double* d_alpha = static_cast<double*>(c->d_sched);
   int8_t* d_pol = reinterpret_cast<int8_t*>(static_cast<char*>(c->d_sched) + abytes);
   SP2_HIP(c, hipMemcpyAsync(d_alpha, alpha.data(), abytes,
@@ -1498,6 +1566,75 @@ sp2_status sp2_get_norm_times(sp2_ctx c, int32_t cap, int32_t* len,
 sp2_status sp2_get_history(sp2_ctx c, int32_t cap, int32_t* len, double* v,
                            double* t1, double* t2, int8_t* p, double* r) {
   return sp2_batch_get_history(c, 0, cap, len, v, t1, t2, p, r);
+}
+
+sp2_status sp2_run_dense_noalloc(int device, void* hip_stream,
+                                 const double* F_dev, int64_t n, int64_t ldf,
+                                 double lambda_min, double lambda_max,
+                                 int64_t n_occ, const sp2_options* opt_in,
+                                 void* D_dev, int64_t ldd, int32_t as_fp64,
+                                 int32_t cap, double* v, int32_t* n_iter,
+                                 int32_t* n_squares) {
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev ||
+      device >= kScratchDevices)
+    return SP2_INVALID_ARG;
+  sp2_ctx_s ctx;
+  sp2_ctx c = &ctx;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  sp2_options opt;
+  if (opt_in) {
+    opt = *opt_in;
+  } else {
+    sp2_default_options(&opt);
+  }
+  sp2_status st = validate_options(c, opt);
+  if (st != SP2_OK) return st;
+  if (opt.norm != SP2_NORM_FROBENIUS || opt.tail_split > 1 ||
+      opt.kernel_timing != 0 || cap < 0 || (cap > 0 && !v))
+    return SP2_INVALID_ARG;
+  opt.tail_split = 1;   // whole tiles only: no tail workspace
+  st = validate_instance(c, F_dev, n, ldf, lambda_min, lambda_max, n_occ);
+  if (st != SP2_OK) return st;
+  if (!D_dev || ldd < n) return SP2_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return SP2_HIP_ERROR;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            device) == hipSuccess && cus > 0)
+    c->num_cus = cus;
+  st = scratch_on_device(device, &c->arena);
+  if (st != SP2_OK) return st;
+  c->arena_cap = kScratchBytes;
+  size_t nd_cap = 0;
+  if (grow(c, c->d_ndone, nd_cap, 256, c->stream) != hipSuccess)
+    return SP2_INVALID_ARG;
+  HostInst h;
+  h.F = F_dev;
+  h.n = n;
+  h.ldf = ldf;
+  h.lmin = lambda_min;
+  h.lmax = lambda_max;
+  h.n_occ = n_occ;
+  c->hi.assign(1, h);
+  c->bsr = false;
+  c->opt = opt;
+  c->fp64_store = (opt.precision == SP2_FP64);
+  st = setup(c);
+  // workspaces that do not fit the scratch: the input is too large
+  if (st == SP2_OUT_OF_MEMORY) return SP2_INVALID_ARG;
+  if (st != SP2_OK) return st;
+  c->inited = true;
+  st = run_batch(c);
+  if (st != SP2_OK) return st;
+  st = copy_density(c, 0, D_dev, ldd, as_fp64);
+  if (st != SP2_OK) return st;
+  const DevState& hs = c->host_state[0];
+  const int sq = c->hi[0].trivial ? 0 : hs.squares;
+  if (n_iter) *n_iter = hs.n;
+  if (n_squares) *n_squares = sq;
+  for (int k = 0; k < cap; ++k) v[k] = k < sq ? hs.v[k] : NAN;
+  return static_cast<sp2_status>(hs.status);
 }
 
 }  // extern "C"
