@@ -1,5 +1,6 @@
 """CPU checks of the seeded input generators (no method arithmetic here)."""
 import numpy as np
+import pytest
 
 from workloads import dense_instance, batch_instances, two_band_spectrum
 from workloads.banded import banded_instance, to_bsr_blocks, givens_brick_wall
@@ -66,3 +67,33 @@ def test_bsr_blocks_round_trip_with_padding():
     # the block pattern is symmetric
     pat = {(r, c) for r in range(nb) for c in ci[rp[r]:rp[r + 1]]}
     assert all((c, r) in pat for r, c in pat)
+
+
+def test_decay_band_entries_and_structure():
+    from workloads.decay_band import decay_band, alternating_diagonal
+    A = decay_band(400, 40, 8.0, np.random.default_rng(6)).toarray()
+    assert np.array_equal(A, A.T) and not np.any(np.diag(A))
+    i, j = np.nonzero(A)
+    assert np.max(np.abs(i - j)) == 40
+    # scaled back by exp(|i - j| / 8) the entries are standard normal
+    z = A[i, j] * np.exp(np.abs(i - j) / 8.0)
+    assert abs(np.mean(z)) < 0.03 and abs(np.mean(z * z) - 1.0) < 0.05
+    assert np.array_equal(alternating_diagonal(5), [-1.0, 1.0, -1.0, 1.0, -1.0])
+
+
+@pytest.mark.parametrize("n,seed", [(512, 3), (1024, 11)])
+def test_decay_band_instance_gap_bounds_and_inertia(n, seed):
+    from workloads.decay_band import count_below, decay_band_instance
+    inst = decay_band_instance(n=n, seed=seed)
+    F = inst.F.toarray()
+    ev = np.linalg.eigvalsh(F)
+    k = inst.n_occ
+    assert k == n // 2
+    assert abs(ev[k - 1] - inst.homo) < 1e-12 and abs(ev[k] - inst.lumo) < 1e-12
+    assert abs(inst.gap - 0.1) <= 1e-4
+    assert inst.lambda_min <= ev[0] and inst.lambda_max >= ev[-1]
+    assert ev[0] - inst.lambda_min < 1e-5 and inst.lambda_max - ev[-1] < 1e-5
+    d = np.diag(F)
+    assert np.all(d[0::2] == -inst.delta) and np.all(d[1::2] == inst.delta)
+    for s in (-3.0, inst.homo - 1e-3, 0.5 * (inst.homo + inst.lumo), 2.5):
+        assert count_below(inst.F, s) == int(np.count_nonzero(ev < s))
