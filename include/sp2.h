@@ -346,10 +346,12 @@ sp2_status sp2_batch_get_run_time(sp2_ctx ctx, double* run_ms,
  *   - if the stop has not fired at step n_max, X~_{n_max} is returned with
  *     n = n_max and SP2_OK;
  *   - homo_in > lambda_min and lumo_in < lambda_max are required.
- * Each step still computes one square S = X~_{i-1}^2 and forms
- * X_i = a S + b X~_{i-1} + c I in the square's epilogue with
- * (a, b, c) = (alpha^2, 2 alpha (1 - alpha), (1 - alpha)^2) for p_i = 1 and
- * (-alpha^2, 2 alpha, 0) for p_i = 0.
+ * Each step computes one square, of the matrix the polynomial is applied
+ * to: the epilogue of the previous step (the affine start for step 1)
+ * stores Y_i = alpha_i X~_{i-1} + (1 - alpha_i) I for p_i = 1 and
+ * Y_i = alpha_i X~_{i-1} for p_i = 0, the square kernel forms S = Y_i^2 and
+ * X_i = S or 2 Y_i - S, and the error of X~_{i-1} is taken from Y_i and S
+ * in FP64. The returned iterate is recovered from its stored matrix.
  * --------------------------------------------------------------------- */
 
 /* Alg. 3 alone, on the host (no device, no context). accelerate = 0 uses
@@ -396,8 +398,11 @@ sp2_status sp2_set_homo_lumo(sp2_ctx ctx, int32_t count,
  * after (the Frobenius estimate can stop too early while it is on); with
  * SP2_NORM_SPECTRAL the stretch stays on and the stop is tested from step 1
  * as printed.
- * Each step computes two products, S = X~^2 (which also gives e_{i-1}) and
- * X~ S, and forms the new iterate from them in the second one's epilogue.
+ * Each step computes two products of the stretched matrix X_s (stored by
+ * the previous step's epilogue), S = X_s^2 (which also gives e_{i-1}, from
+ * X_s and S in FP64) and X_s S, and forms 3 S - 2 X_s S in the second
+ * one's epilogue. The stretches come from the beta recursion, evaluated on
+ * the host at this call.
  * --------------------------------------------------------------------- */
 
 /* Switches the instances of the last sp2_init_dense or sp2_batch_init to

@@ -198,9 +198,14 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     }
     return;
   }
-  const StepCoef k = step_coef(st->p[iter], st->alpha[iter]);
-  const float ka = static_cast<float>(k.ca), kb = static_cast<float>(k.cb),
-              kc = static_cast<float>(k.cc);
+  // the step squares the stored Y = a X~ + c I (OpMap); X_i = S or 2 Y - S,
+  // the error of X~ from Y and S, and the stored output is the next step's
+  // matrix an X~_i + cn I
+  const bool p1 = st->p[iter] != 0;
+  const StepCoef k{st->ecoef[0], st->ecoef[1], st->ecoef[2], st->ecoef[3],
+                   st->ecoef[4]};
+  const bool stretch = st->stretch != 0;
+  const float ka = p1 ? 1.f : -1.f, kb = p1 ? 0.f : 2.f;
   const double tau = in.tau;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
@@ -265,13 +270,15 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       if (I == J && m > c) continue;
       const float s = acc[j];
       const float xo = old ? *gro(old + m * BS + c) : 0.f;
-      const double d = static_cast<double>(xo) - static_cast<double>(s);
+      // identity terms only inside the matrix proper
+      const bool on = (I == J && m == c && I * BS + m < n);
+      const double d = __builtin_fma(k.es, static_cast<double>(s),
+                                     k.ey * static_cast<double>(xo)) +
+                       (on ? k.ei : 0.0);
       const double w = (I == J && m == c) ? 1.0 : 2.0;
       sv += w * d * d;
       bsq += (I == J) ? w * d * d : d * d;
-      // X_i = ca S + cb X~ + cc I (identity only inside the matrix proper)
       float xn = __builtin_fmaf(kb, xo, ka * s);
-      if (I == J && m == c && I * BS + m < n) xn += kc;
       double xd = static_cast<double>(xn);
       if (fabs(xd) < tau) {
         xn = 0.f;
@@ -280,6 +287,7 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
       st2 += w * xd * xd;
       if (I == J && m == c) st1 += xd;
       nz = nz || (xn != 0.f);
+      if (stretch) xn = static_cast<float>(__builtin_fma(k.an, xd, on ? k.cn : 0.0));
       *grw(out + m * BS + c) = xn;
       if (!(I == J && m == c)) *grw(outT + c * BS + m) = xn;
     }
@@ -328,6 +336,8 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(
   const int I = X.brow[q], J = X.col[q];
   const int n_occ = static_cast<int>(in.prm.n_occ);
   const int trivial = (n_occ == 0) ? 1 : (n_occ == n ? 2 : 0);
+  const OpMap m1 = step_map(in, 1);
+  const bool stretch = (m1.a != 1.0 || m1.c != 0.0);
   double t1 = 0.0, t2 = 0.0;
   bool nz = false;
   for (int e = threadIdx.x; e < BE; e += 256) {
@@ -345,7 +355,12 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(
     }
     const float xs = static_cast<float>(x);
     const double xd = static_cast<double>(xs);
-    X.val[static_cast<size_t>(q) * BE + e] = xs;
+    // stored: the matrix of step 1 (a X~_0 + c I with a stretch)
+    X.val[static_cast<size_t>(q) * BE + e] =
+        (stretch && !trivial)
+            ? static_cast<float>(__builtin_fma(m1.a, xd,
+                                               (gi == gj && gi < n) ? m1.c : 0.0))
+            : xs;
     t2 += xd * xd;
     if (gi == gj) t1 += xd;
     nz = nz || (xs != 0.f);
@@ -374,22 +389,31 @@ __global__ void bsr_reset_kernel(BsrCounters* ctr) {
   for (int i = threadIdx.x; i < words; i += blockDim.x) w[i] = 0;
 }
 
-// Gathers the blocks listed by idx.pos into a compact array (FP64 or FP32).
+// Gathers the blocks listed by idx.pos into a compact array (FP64 or FP32),
+// as (x - c [diagonal]) / a: the returned iterate from its stored matrix.
 template <typename To>
 __global__ __launch_bounds__(256) void bsr_gather_kernel(
-    const float* __restrict__ val, const int32_t* __restrict__ pos, int cnt,
-    To* __restrict__ out) {
+    const float* __restrict__ val, const int32_t* __restrict__ brow,
+    const int32_t* __restrict__ bcol, const int32_t* __restrict__ pos, int cnt,
+    int n, OpMap m, To* __restrict__ out) {
   for (int b = blockIdx.x; b < cnt; b += gridDim.x) {
-    const float* src = val + static_cast<size_t>(pos[b]) * BE;
-    for (int e = threadIdx.x; e < BE; e += 256)
-      out[static_cast<size_t>(b) * BE + e] = static_cast<To>(src[e]);
+    const int p = pos[b];
+    const float* src = val + static_cast<size_t>(p) * BE;
+    const bool dblk = (brow[p] == bcol[p]);
+    for (int e = threadIdx.x; e < BE; e += 256) {
+      const int i = e / BS, j = e % BS;
+      const bool on = dblk && i == j && brow[p] * BS + i < n;
+      out[static_cast<size_t>(b) * BE + e] = static_cast<To>(
+          (static_cast<double>(src[e]) - (on ? m.c : 0.0)) / m.a);
+    }
   }
 }
 
-// Expands the nonzero blocks into a dense n x n matrix (zero elsewhere).
+// Expands the nonzero blocks into a dense n x n matrix (zero elsewhere),
+// as (x - c [diagonal]) / a.
 template <typename To>
 __global__ __launch_bounds__(256) void bsr_to_dense_kernel(
-    const float* __restrict__ val, BsrIndex idx, int nb, int n,
+    const float* __restrict__ val, BsrIndex idx, int nb, int n, OpMap m,
     To* __restrict__ D, int64_t ldd) {
   const int I = blockIdx.x;
   for (int b = idx.ptr[I]; b < idx.ptr[I + 1]; ++b) {
@@ -397,7 +421,9 @@ __global__ __launch_bounds__(256) void bsr_to_dense_kernel(
     const float* src = val + static_cast<size_t>(idx.pos[b]) * BE;
     for (int e = threadIdx.x; e < BE; e += 256) {
       const int gi = I * BS + e / BS, gj = J * BS + e % BS;
-      if (gi < n && gj < n) D[gi * ldd + gj] = static_cast<To>(src[e]);
+      if (gi < n && gj < n)
+        D[gi * ldd + gj] = static_cast<To>(
+            (static_cast<double>(src[e]) - (gi == gj ? m.c : 0.0)) / m.a);
     }
   }
   (void)nb;
@@ -453,27 +479,30 @@ hipError_t launch_bsr_f0(const double* F, const BsrMat& X, int nnzb,
   return hipGetLastError();
 }
 
-hipError_t launch_bsr_gather(const float* val, const int32_t* pos, int cnt,
-                             void* out, bool fp64, hipStream_t s) {
+hipError_t launch_bsr_gather(const BsrMat& M, const int32_t* pos, int cnt,
+                             int n, OpMap m, void* out, bool fp64,
+                             hipStream_t s) {
   const int g = cnt < 4096 ? (cnt > 0 ? cnt : 1) : 4096;
   if (fp64)
-    hipLaunchKernelGGL(bsr_gather_kernel<double>, dim3(g), dim3(256), 0, s, val,
-                       pos, cnt, static_cast<double*>(out));
+    hipLaunchKernelGGL(bsr_gather_kernel<double>, dim3(g), dim3(256), 0, s,
+                       M.val, M.brow, M.col, pos, cnt, n, m,
+                       static_cast<double*>(out));
   else
-    hipLaunchKernelGGL(bsr_gather_kernel<float>, dim3(g), dim3(256), 0, s, val,
-                       pos, cnt, static_cast<float*>(out));
+    hipLaunchKernelGGL(bsr_gather_kernel<float>, dim3(g), dim3(256), 0, s,
+                       M.val, M.brow, M.col, pos, cnt, n, m,
+                       static_cast<float*>(out));
   return hipGetLastError();
 }
 
 hipError_t launch_bsr_to_dense(const float* val, const BsrIndex& idx, int nb,
-                               int n, void* D, int64_t ldd, bool fp64,
+                               int n, OpMap m, void* D, int64_t ldd, bool fp64,
                                hipStream_t s) {
   if (fp64)
     hipLaunchKernelGGL(bsr_to_dense_kernel<double>, dim3(nb), dim3(256), 0, s,
-                       val, idx, nb, n, static_cast<double*>(D), ldd);
+                       val, idx, nb, n, m, static_cast<double*>(D), ldd);
   else
     hipLaunchKernelGGL(bsr_to_dense_kernel<float>, dim3(nb), dim3(256), 0, s,
-                       val, idx, nb, n, static_cast<float*>(D), ldd);
+                       val, idx, nb, n, m, static_cast<float*>(D), ldd);
   return hipGetLastError();
 }
 

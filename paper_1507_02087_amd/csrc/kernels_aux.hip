@@ -18,10 +18,8 @@ __device__ __forceinline__ double c_sp2() {
 }
 // q~ of sec. 2.
 constexpr double kQTilde = 1.8;
-// sec. 3: C_2 of the McWeeny and McW-ACC expansions, and the beta below
-// which McW-ACC switches its stretch off.
+// sec. 3: C_2 of the McWeeny and McW-ACC expansions.
 constexpr double kCMcWeeny = 4.0;
-constexpr double kMwDelta = 0.01;
 
 __device__ __forceinline__ double wave_sum(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -72,9 +70,10 @@ __global__ __launch_bounds__(kThreads) void state_reset_kernel(
 
 // X_0 = (lambda_max I - F) / (lambda_max - lambda_min) in FP64 (Alg. 2),
 // truncated (|x| < tau -> 0, sec. 5), rounded to the storage type, with the
-// padding region set to zero; X_0 = 0 or I when n_occ is 0 or n. Each block
+// padding region set to zero; X_0 = 0 or I when n_occ is 0 or n. With a
+// stretch on step 1 the buffer receives a X~_0 + c I (OpMap). Each block
 // handles kF0Rows rows of one instance and writes one partial triple
-// (0, Tr, sum x^2).
+// (0, Tr, sum x^2) of X~_0.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void f0_kernel(
     const Instance* __restrict__ insts, const F0Item* __restrict__ items,
@@ -88,6 +87,10 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
   T* X = static_cast<T*>(in.X[0]);
   __bf16* XH = static_cast<__bf16*>(in.XH[0]);
   __bf16* XL = static_cast<__bf16*>(in.XL[0]);
+  // stored: the matrix step 1 squares, a X~_0 + c I (OpMap; X~_0 itself
+  // without a stretch and for n_occ = 0 or n)
+  const OpMap m1 = step_map(in, 1);
+  const bool stretch = !trivial && (m1.a != 1.0 || m1.c != 0.0);
   double t1 = 0.0, t2 = 0.0;
   for (int rr = 0; rr < kF0Rows; ++rr) {
     const int i = it.row0 + rr;
@@ -104,8 +107,11 @@ __global__ __launch_bounds__(kThreads) void f0_kernel(
           if (fabs(x) < in.tau) x = 0.0;
         }
       }
-      const T xs = static_cast<T>(x);
-      const double xd = static_cast<double>(xs);
+      const T xt = static_cast<T>(x);
+      const double xd = static_cast<double>(xt);
+      const T xs = stretch ? static_cast<T>(__builtin_fma(
+                                 m1.a, xd, (i == j && i < n) ? m1.c : 0.0))
+                           : xt;
       Xi[j] = xs;
       if (XH) {
         const float xf = static_cast<float>(xs);
@@ -324,7 +330,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
       return;
     }
     if (mw) {
-      if (st->mw_first > 0 && k >= st->mw_first && !isnan(r) && r < kQTilde) {
+      if (k >= prm.mw_first && !isnan(r) && r < kQTilde) {
         publish(st, ndone, count, mirror, 0, k);   // McWeeny stop (sec. 3)
         return;
       }
@@ -351,31 +357,15 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   // Polynomial of the next step: from the schedule (Alg. 4), or from the
   // traces of X~_iter (Alg. 2 branch). Past the schedule's end one more
   // square is needed for v_{n_max}; the iterate it yields is not used.
-  // McWeeny: the stretch of McW-ACC from beta, switched off (and the stop
-  // enabled from the step after) once beta < 0.01 with the Frobenius or the
-  // mixed norm; the regular expansion, and McW-ACC with the spectral norm,
-  // test the stop from step 1.
+  // McWeeny: one polynomial; the stretch of McW-ACC from the host's table
+  // (computed from the beta recursion at set-up, switched off once
+  // beta < 0.01 with the Frobenius or the mixed norm).
   int pn;
   double an = 1.0;
   if (mw) {
-    if (iter == 0) {
-      st->mw_beta = prm.mw_beta0;
-      st->mw_stretch = prm.mw_acc;
-      st->mw_first = (prm.mw_acc && prm.norm != 2) ? 0 : 1;
-    }
     const int i = iter + 1;
-    // with the spectral norm the stretch stays on and every step is tested
-    if (st->mw_stretch && prm.norm != 2 && st->mw_beta < kMwDelta) {
-      st->mw_stretch = 0;
-      st->mw_first = i + 1;
-    }
     pn = 1;
-    if (st->mw_stretch) {
-      const double be = st->mw_beta;
-      an = 3.0 / sqrt(12.0 * be * be - 18.0 * be + 9.0);
-      const double bs = an * (be - 0.5) + 0.5;
-      st->mw_beta = 3.0 * bs * bs - 2.0 * bs * bs * bs;
-    }
+    if (i <= prm.mw_len) an = in.sched_alpha[i];
   } else if (sched) {
     const int i = iter + 1;
     if (i <= prm.n_max) {
@@ -391,27 +381,40 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
   }
   st->p[iter + 1] = static_cast<int8_t>(pn);
   st->alpha[iter + 1] = an;
+  // epilogue coefficients of step iter + 1: the error of X~_iter from the
+  // stored matrix of that step and its square, and the map of the matrix
+  // it stores for step iter + 2
+  const OpMap nxt = step_map(in, iter + 2);
+  const StepCoef e = step_coef(op_map(prm.method, pn, an), nxt);
+  st->ecoef[0] = e.ey;
+  st->ecoef[1] = e.es;
+  st->ecoef[2] = e.ei;
+  st->ecoef[3] = e.an;
+  st->ecoef[4] = e.cn;
+  st->stretch = (nxt.a != 1.0 || nxt.c != 0.0) ? 1 : 0;
 }
 
+// D = (X - c I) / a (OpMap m; a = 1, c = 0 copies exactly).
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void copy_out_kernel(
-    const Tin* __restrict__ X, int n, int ldx, Tout* __restrict__ D,
+    const Tin* __restrict__ X, int n, int ldx, OpMap m, Tout* __restrict__ D,
     int64_t ldd) {
   const int64_t total = static_cast<int64_t>(n) * n;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
        e < total; e += static_cast<int64_t>(gridDim.x) * kThreads) {
     const int64_t i = e / n, j = e % n;
-    D[i * ldd + j] = static_cast<Tout>(X[i * ldx + j]);
+    const double x = static_cast<double>(X[i * ldx + j]);
+    D[i * ldd + j] = static_cast<Tout>((x - (i == j ? m.c : 0.0)) / m.a);
   }
 }
 
-// D = X for a symmetric X of which only the upper triangle is current:
-// block (bi, bj) of 32 x 32 with bi <= bj reads the upper tile through LDS
-// and writes it and its transpose, both as rows (coalesced). Blocks with
-// bi > bj have nothing to do.
+// D = (X - c I) / a for a symmetric X of which only the upper triangle is
+// current: block (bi, bj) of 32 x 32 with bi <= bj reads the upper tile
+// through LDS and writes it and its transpose, both as rows (coalesced).
+// Blocks with bi > bj have nothing to do.
 template <typename Tin, typename Tout>
 __global__ __launch_bounds__(kThreads) void copy_out_sym_kernel(
-    const Tin* __restrict__ X, int n, int ldx, Tout* __restrict__ D,
+    const Tin* __restrict__ X, int n, int ldx, OpMap m, Tout* __restrict__ D,
     int64_t ldd) {
   constexpr int B = 32;
   __shared__ Tin t[B][B + 1];
@@ -424,13 +427,16 @@ __global__ __launch_bounds__(kThreads) void copy_out_sym_kernel(
     if (i < n && j < n) t[r][c] = X[static_cast<int64_t>(i) * ldx + j];
   }
   __syncthreads();
+  auto val = [&](Tin x, bool diag) {
+    return static_cast<Tout>((static_cast<double>(x) - (diag ? m.c : 0.0)) / m.a);
+  };
   for (int e = threadIdx.x; e < B * B; e += kThreads) {
     const int r = e / B, c = e % B;
     const int i = i0 + r, j = j0 + c;
     if (i < n && j < n) {
       // on a diagonal tile the lower part comes from the transposed position
       const Tin x = (bi == bj && r > c) ? t[c][r] : t[r][c];
-      D[static_cast<int64_t>(i) * ldd + j] = static_cast<Tout>(x);
+      D[static_cast<int64_t>(i) * ldd + j] = val(x, i == j);
     }
   }
   if (bi == bj) return;
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void copy_out_sym_kernel(
     const int r = e / B, c = e % B;
     const int i = j0 + r, j = i0 + c;
     if (i < n && j < n)
-      D[static_cast<int64_t>(i) * ldd + j] = static_cast<Tout>(t[c][r]);
+      D[static_cast<int64_t>(i) * ldd + j] = val(t[c][r], false);
   }
 }
 
@@ -481,37 +487,37 @@ hipError_t launch_finalize(const Instance* inst, int count,
 
 hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
                            void* D, int64_t ldd, bool out_fp64, bool symmetric,
-                           hipStream_t s) {
+                           OpMap m, hipStream_t s) {
   if (symmetric) {
     const int nb = (n + 31) / 32;
     const dim3 grid(nb, nb);
     if (fp64_store)
       hipLaunchKernelGGL((copy_out_sym_kernel<double, double>), grid,
                          dim3(kThreads), 0, s, static_cast<const double*>(X), n,
-                         ldx, static_cast<double*>(D), ldd);
+                         ldx, m, static_cast<double*>(D), ldd);
     else if (out_fp64)
       hipLaunchKernelGGL((copy_out_sym_kernel<float, double>), grid,
                          dim3(kThreads), 0, s, static_cast<const float*>(X), n,
-                         ldx, static_cast<double*>(D), ldd);
+                         ldx, m, static_cast<double*>(D), ldd);
     else
       hipLaunchKernelGGL((copy_out_sym_kernel<float, float>), grid,
                          dim3(kThreads), 0, s, static_cast<const float*>(X), n,
-                         ldx, static_cast<float*>(D), ldd);
+                         ldx, m, static_cast<float*>(D), ldd);
     return hipGetLastError();
   }
   const int g = grid_for(static_cast<int64_t>(n) * n);
   if (fp64_store) {
     hipLaunchKernelGGL((copy_out_kernel<double, double>), dim3(g),
                        dim3(kThreads), 0, s, static_cast<const double*>(X), n,
-                       ldx, static_cast<double*>(D), ldd);
+                       ldx, m, static_cast<double*>(D), ldd);
   } else if (out_fp64) {
     hipLaunchKernelGGL((copy_out_kernel<float, double>), dim3(g),
                        dim3(kThreads), 0, s, static_cast<const float*>(X), n,
-                       ldx, static_cast<double*>(D), ldd);
+                       ldx, m, static_cast<double*>(D), ldd);
   } else {
     hipLaunchKernelGGL((copy_out_kernel<float, float>), dim3(g),
                        dim3(kThreads), 0, s, static_cast<const float*>(X), n,
-                       ldx, static_cast<float*>(D), ldd);
+                       ldx, m, static_cast<float*>(D), ldd);
   }
   return hipGetLastError();
 }

@@ -98,11 +98,18 @@ struct sp2_ctx_s {
   void* s_split[2] = {nullptr, nullptr};
   size_t s_split_cap[2] = {0, 0};
   bool mcweeny = false;
+  // some instance's schedule stretches a step (alpha != 1): the square
+  // kernels with the stretch coefficients run
+  bool stretch = false;
   Instance* d_inst = nullptr;
   size_t d_inst_cap = 0;
   std::vector<Instance> h_inst;    // host copy of the instance table
   void* d_sched = nullptr;         // SP2-ACC schedules: alphas, then p's
   size_t d_sched_cap = 0;
+  // host copies of the schedule tables (kMaxIter + 2 entries per instance):
+  // SP2-ACC's p and alpha, or McW-ACC's alpha
+  std::vector<double> h_sched_alpha;
+  std::vector<int8_t> h_sched_p;
   float* d_blk = nullptr;          // block norms of the mixed norm
   size_t d_blk_cap = 0;
   double* d_lz = nullptr;          // Lanczos bases of the mixed norm
@@ -591,6 +598,7 @@ sp2_status setup(sp2_ctx c) {
                             hipMemcpyHostToDevice, s));
   c->h_inst = inst;
   c->mcweeny = false;
+  c->stretch = false;
   if (!tiles.empty())
     SP2_HIP(c, hipMemcpyAsync(c->d_tiles, tiles.data(),
                               tiles.size() * sizeof(int2),
@@ -648,6 +656,7 @@ sp2_status run_batch(sp2_ctx c) {
 
   sp2::SquareArgs a;
   a.mode = 0;
+  a.stretch = c->stretch ? 1 : 0;
   a.mirror32 = 1;
   a.inst = c->d_inst;
   a.tiles = c->d_tiles;
@@ -784,6 +793,22 @@ sp2_status bsr_result_index(sp2_ctx c, int64_t* nnzb) {
   return SP2_OK;
 }
 
+// Map of the matrix stored for the returned iterate X~_n of instance idx:
+// its buffer holds the operand of step n + 1 (OpMap; the identity without
+// a stretch and for n_occ = 0 or n).
+sp2::OpMap result_map(const sp2_ctx c, int idx) {
+  const sp2::OpMap id{1.0, 0.0};
+  if (c->hi[idx].trivial || c->h_inst.empty()) return id;
+  const sp2::StopParams& prm = c->h_inst[idx].prm;
+  const int i = c->host_state[idx].n + 1;
+  const size_t o = static_cast<size_t>(idx) * (sp2::kMaxIter + 2) + i;
+  if (prm.method == 1)
+    return sp2::op_map(1, 1, (i <= prm.mw_len) ? c->h_sched_alpha[o] : 1.0);
+  if (prm.n_max > 0 && i <= prm.n_max)
+    return sp2::op_map(0, c->h_sched_p[o], c->h_sched_alpha[o]);
+  return id;
+}
+
 sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
                         int32_t as_fp64) {
   if (c->bsr) {
@@ -798,7 +823,8 @@ sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
                                 c->stream));
     const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
     SP2_HIP(c, sp2::launch_bsr_to_dense(m.val, c->b.idx, c->b.nb,
-                                        static_cast<int>(c->b.n), D_dev, ldd,
+                                        static_cast<int>(c->b.n),
+                                        result_map(c, 0), D_dev, ldd,
                                         as_fp64 != 0, c->stream));
     SP2_HIP(c, hipStreamSynchronize(c->stream));
     return SP2_OK;
@@ -816,7 +842,8 @@ sp2_status copy_density(sp2_ctx c, int idx, void* D_dev, int64_t ldd,
                    c->opt.norm != SP2_NORM_SPECTRAL;
   SP2_HIP(c, sp2::launch_copy_out(X, c->fp64_store, static_cast<int>(h.n),
                                   static_cast<int>(h.ld), D_dev, ldd,
-                                  as_fp64 != 0, sym, c->stream));
+                                  as_fp64 != 0, sym, result_map(c, idx),
+                                  c->stream));
   SP2_HIP(c, hipStreamSynchronize(c->stream));
   return SP2_OK;
 }
@@ -1236,6 +1263,7 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   SP2_HIP(c, hipStreamSynchronize(s));
   c->h_inst.assign(1, in);
   c->mcweeny = false;
+  c->stretch = false;
   release_groups(c);
   HostInst h;
   h.F = nullptr;
@@ -1280,9 +1308,9 @@ sp2_status sp2_get_bsr(sp2_ctx c, int32_t* row_ptr_dev, int32_t* col_idx_dev,
                               nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice,
                               s));
     const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
-    SP2_HIP(c, sp2::launch_bsr_gather(m.val, c->b.idx.pos,
-                                      static_cast<int>(nnzb), blocks_dev,
-                                      as_fp64 != 0, s));
+    SP2_HIP(c, sp2::launch_bsr_gather(m, c->b.idx.pos, static_cast<int>(nnzb),
+                                      static_cast<int>(c->b.n), result_map(c, 0),
+                                      blocks_dev, as_fp64 != 0, s));
   }
   SP2_HIP(c, hipStreamSynchronize(s));
   return SP2_OK;
@@ -1411,6 +1439,42 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
   if (split)
     for (int q = 0; q < 2; ++q)
       SP2_HIP(c, grow(c, c->s_split[q], c->s_split_cap[q], pool_elems * 2, s));
+  // McW-ACC (sec. 3): the stretch of every step from the scalar recursion
+  // beta_i = p_mw(alpha_i (beta_{i-1} - 1/2) + 1/2), beta_0 = (1 - xi /
+  // gamma) / 2, alpha_i = 3 / sqrt(12 beta^2 - 18 beta + 9); with the
+  // Frobenius or the mixed norm the stretch is switched off once beta < 0.01
+  // and the stop is tested from the step after (reading R24); with the
+  // spectral norm the stretch stays on and every step is tested.
+  const int L = sp2::kMaxIter + 2;
+  std::vector<double> alpha(static_cast<size_t>(count) * L, 1.0);
+  std::vector<int> mw_len(count, 0), mw_first(count, 1);
+  const bool spectral = (c->opt.norm == SP2_NORM_SPECTRAL);
+  for (int b = 0; b < count && xi; ++b) {
+    const HostInst& h = c->hi[b];
+    const double gam = 2.0 * std::max(h.lmax - mu[b], mu[b] - h.lmin);
+    double beta = 0.5 * (1.0 - xi[b] / gam);
+    mw_first[b] = sp2::kMaxIter + 2;   // until the stretch is switched off
+    for (int i = 1; i <= sp2::kMaxIter + 1; ++i) {
+      if (!spectral && beta < 0.01) {
+        mw_first[b] = i + 1;
+        break;
+      }
+      const double a = 3.0 / sqrt(12.0 * beta * beta - 18.0 * beta + 9.0);
+      alpha[static_cast<size_t>(b) * L + i] = a;
+      mw_len[b] = i;
+      const double bs = a * (beta - 0.5) + 0.5;
+      beta = 3.0 * bs * bs - 2.0 * bs * bs * bs;
+    }
+    if (spectral) mw_first[b] = 1;
+  }
+  const size_t abytes = alpha.size() * sizeof(double);
+  SP2_HIP(c, grow(c, c->d_sched, c->d_sched_cap, abytes, s));
+  SP2_HIP(c, hipMemcpyAsync(c->d_sched, alpha.data(), abytes,
+                            hipMemcpyHostToDevice, s));
+  c->h_sched_alpha = alpha;
+  c->h_sched_p.assign(alpha.size(), 1);
+  c->stretch = std::any_of(alpha.begin(), alpha.end(),
+                           [](double x) { return x != 1.0; });
   for (int b = 0; b < count; ++b) {
     const HostInst& h = c->hi[b];
     Instance& in = c->h_inst[b];
@@ -1422,8 +1486,10 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
     in.SH = split ? static_cast<char*>(c->s_split[0]) + h.xoff * 2 : nullptr;
     in.SL = split ? static_cast<char*>(c->s_split[1]) + h.xoff * 2 : nullptr;
     in.prm.method = 1;
-    in.prm.mw_acc = xi ? 1 : 0;
-    in.prm.mw_beta0 = xi ? 0.5 * (1.0 - xi[b] / gam) : 0.0;
+    in.prm.mw_first = mw_first[b];
+    in.prm.mw_len = mw_len[b];
+    in.sched_alpha = static_cast<const double*>(c->d_sched) +
+                     static_cast<size_t>(b) * L;
   }
   SP2_HIP(c, hipMemcpyAsync(c->d_inst, c->h_inst.data(),
                             count * sizeof(Instance), hipMemcpyHostToDevice, s));
@@ -1502,6 +1568,10 @@ sp2_status sp2_set_homo_lumo(sp2_ctx c, int32_t count, const double* homo_out,
   hipStream_t s = c->stream;
   const size_t abytes = alpha.size() * sizeof(double);
   SP2_HIP(c, grow(c, c->d_sched, c->d_sched_cap, abytes + pol.size(), s));
+  c->h_sched_alpha = alpha;
+  c->h_sched_p = pol;
+  c->stretch = std::any_of(alpha.begin(), alpha.end(),
+                           [](double x) { return x != 1.0; });
   double* d_alpha = static_cast<double*>(c->d_sched);
   int8_t* d_pol = reinterpret_cast<int8_t*>(static_cast<char*>(c->d_sched) + abytes);
   SP2_HIP(c, hipMemcpyAsync(d_alpha, alpha.data(), abytes,

@@ -51,14 +51,16 @@ struct DevState {
   // Frobenius norm: the mixed norm, or the spectral norm of Alg. 2
   double m[kMaxIter + 1];
   int32_t krylov[kMaxIter + 1];   // Lanczos steps behind m[k]
-  // McWeeny (sec. 3): the stretch's beta, whether the stretch is on, and
-  // the first step whose error the stop may test (0: none yet)
-  double mw_beta;
-  int32_t mw_stretch;
-  int32_t mw_first;
   double t1[kMaxIter + 2];
   double t2[kMaxIter + 2];
   double r[kMaxIter + 1];
+  // epilogue coefficients (StepCoef: ey, es, ei, an, cn) of the next step to
+  // run, written by the finalize kernel when it chooses that step's
+  // polynomial, and whether that step's output is stretched (an != 1 or
+  // cn != 0); precomputed so that the square kernels load them as scalars
+  double ecoef[5];
+  int32_t stretch;
+  int32_t pad;
 };
 
 // Outcome of the whole batch, in host-coherent pinned memory, written by the
@@ -80,23 +82,11 @@ struct StopParams {
   int32_t n_max;     // schedule length; 0 = no schedule (Alg. 2 branch)
   int32_t norm;      // error fed to the stop: 0 Frobenius, 1 mixed, 2 spectral
   int32_t method;    // 0 SP2 (Alg. 2, or Alg. 4 with a schedule), 1 McWeeny
-  int32_t mw_acc;    // McWeeny: 1 = McW-ACC with mw_beta0
-  int32_t pad;
-  double mw_beta0;   // McW-ACC: 0.5 (1 - xi / gamma)
+  // McWeeny: first step whose error the stop tests, and the number of steps
+  // with a stretch in the table sched_alpha (alpha = 1 after them)
+  int32_t mw_first;
+  int32_t mw_len;
 };
-
-// McWeeny step written in the two products it computes, S = X~^2 and
-// T = X~ S: with X_s = a (X~ - I/2) + I/2 and b = (1 - a)/2,
-// 3 X_s^2 - 2 X_s^3 = c3 T + c2 S + c1 X~ + c0 I (sec. 3, Alg. McW-ACC);
-// a = 1 gives 3 S - 2 T.
-struct MwCoef {
-  double c3, c2, c1, c0;
-};
-__host__ __device__ __forceinline__ MwCoef mw_coef(double a) {
-  const double b = 0.5 * (1.0 - a);
-  return MwCoef{-2.0 * a * a * a, 3.0 * a * a - 6.0 * a * a * b,
-                6.0 * a * b - 6.0 * a * b * b, 3.0 * b * b - 2.0 * b * b * b};
-}
 
 // Edge of the blocks of the mixed norm (the block size of sec. 6), and the
 // largest Krylov dimension used to find its spectral norm.
@@ -141,17 +131,35 @@ __host__ __device__ __forceinline__ SpecView spec_view(double* base, int n) {
   return v;
 }
 
-// Step i's polynomial written in the square S = X~_{i-1}^2 that the step
-// computes: X_i = ca S + cb X~_{i-1} + cc I. Alg. 4: p = 1 expands
-// ((1 - a) I + a X~)^2 to (a^2, 2a(1 - a), (1 - a)^2), p = 0 expands
-// 2a X~ - (a X~)^2 to (-a^2, 2a, 0). With a = 1 these are exactly Alg. 2's
-// S and 2X~ - S.
-struct StepCoef {
-  double ca, cb, cc;
+// The matrix a step squares (Alg. 4; X_s of Alg. McW-ACC, sec. 3). The
+// buffer that feeds step i holds Y_i = a X~_{i-1} + c I rather than X~_{i-1}:
+//   SP2, p_i = 1:  ((1 - a) I + a X~)^2  ->  c = 1 - a,  X_i = Y^2
+//   SP2, p_i = 0:  2 a X~ - (a X~)^2      ->  c = 0,      X_i = 2 Y - Y^2
+//   McWeeny:       X_s = a (X~ - I/2) + I/2 -> c = (1 - a)/2, X_i = 3 Y^2 - 2 Y^3
+// so every step applies the plain polynomial to the square of the stored
+// matrix, whose rounding is not scaled by the stretch. Alg. 2 (and every
+// step with the stretch off) has a = 1, c = 0: the buffer holds X~ itself.
+struct OpMap {
+  double a, c;
 };
-__host__ __device__ __forceinline__ StepCoef step_coef(int p, double a) {
-  if (p) return StepCoef{a * a, 2.0 * a * (1.0 - a), (1.0 - a) * (1.0 - a)};
-  return StepCoef{-(a * a), 2.0 * a, 0.0};
+__host__ __device__ __forceinline__ OpMap op_map(int method, int p, double a) {
+  if (method == 1) return OpMap{a, 0.5 * (1.0 - a)};
+  return OpMap{a, p ? 1.0 - a : 0.0};
+}
+
+// Coefficients of one step's epilogue in terms of the stored Y = a X~ + c I
+// and its square S = Y^2 (FP64):
+//   error of X~:   X~ - X~^2 = ey Y + es S + ei I, i.e.
+//                  ((a + 2c) Y - S - c (a + c) I) / a^2
+//   next operand:  Y' = an X~_i + cn I  (the map of the following step)
+struct StepCoef {
+  double ey, es, ei;
+  double an, cn;
+};
+__host__ __device__ __forceinline__ StepCoef step_coef(OpMap m, OpMap next) {
+  const double ia2 = 1.0 / (m.a * m.a);
+  return StepCoef{(m.a + 2.0 * m.c) * ia2, -ia2, -m.c * (m.a + m.c) * ia2,
+                  next.a, next.c};
 }
 
 // One instance as the kernels see it.
@@ -178,7 +186,8 @@ struct Instance {
   double lmax, width;  // lambda_max, lambda_max - lambda_min
   double tau;          // truncation threshold (0 = off)
   StopParams prm;
-  // schedule of Alg. 3, entries 1..prm.n_max (null without a schedule)
+  // schedule of Alg. 3, entries 1..prm.n_max (null without a schedule); for
+  // McW-ACC sched_alpha holds the stretches of steps 1..prm.mw_len
   const int8_t* sched_p;
   const double* sched_alpha;
   // Mixed norm (null unless prm.norm == 1): Frobenius norms of the 32 x 32
@@ -197,6 +206,17 @@ struct Instance {
   double* sp;
   int sp_ch0, sp_nch;
 };
+
+// The map of step i from the schedule tables alone (no device state): the
+// SP2-ACC schedule of Alg. 3 for steps 1..n_max, the McW-ACC stretches for
+// steps 1..mw_len, else a = 1, c = 0 (Alg. 2, and after a schedule).
+__device__ __forceinline__ OpMap step_map(const Instance& in, int i) {
+  if (in.prm.method == 1)
+    return op_map(1, 1, (i >= 1 && i <= in.prm.mw_len) ? in.sched_alpha[i] : 1.0);
+  if (in.prm.n_max > 0 && i >= 1 && i <= in.prm.n_max)
+    return op_map(0, in.sched_p[i], in.sched_alpha[i]);
+  return OpMap{1.0, 0.0};
+}
 
 // One unit of work of a square launch, given per workgroup by the host:
 // inst/slot = instance and global tile index (slot -1: idle), piece =
@@ -259,6 +279,9 @@ struct SquareArgs {
   int split;                  // pieces per tail tile
   int iter;                   // step i: X~_{i-1} -> X~_i
   int mode;                   // 0 SP2 step; McWeeny: 1 S = X~^2, 2 T = X~ S
+  // 1: the run stretches the matrices it squares (SP2-ACC schedule or
+  // McW-ACC): the kernels read the step's coefficients from the state
+  int stretch;
   // 1: the epilogues write the mirror (lower triangle) of the FP32 output;
   // 0: only its bf16 split (configurations with presplit operands, when
   // nothing else reads the FP32 lower triangle during the run)
@@ -306,9 +329,11 @@ hipError_t launch_finalize(const Instance* inst, int count,
                            hipStream_t s);
 // symmetric = true rebuilds the lower triangle from the upper one (for
 // iterates whose FP32 mirror was not written).
+// D = (X - c I) / a (a = 1, c = 0 copies): the returned iterate X~_n from
+// its buffer, which holds the operand a X~_n + c I of the following step.
 hipError_t launch_copy_out(const void* X, bool fp64_store, int n, int ldx,
                            void* D, int64_t ldd, bool out_fp64, bool symmetric,
-                           hipStream_t s);
+                           OpMap m, hipStream_t s);
 
 // ---- Block-sparse (BSR, 32 x 32 FP32 blocks) path.
 constexpr int kBsrBlock = 32;
@@ -357,10 +382,13 @@ hipError_t launch_bsr_numeric(const BsrMat& A, const BsrIndex& idx,
 hipError_t launch_bsr_f0(const double* F, const BsrMat& X, int nnzb,
                          const Instance* inst, int n, double* part,
                          hipStream_t s);
-hipError_t launch_bsr_gather(const float* val, const int32_t* pos, int cnt,
-                             void* out, bool fp64, hipStream_t s);
+// The returned block-sparse iterate as (x - c [diagonal]) / a from its
+// stored matrix (OpMap m of the following step).
+hipError_t launch_bsr_gather(const BsrMat& M, const int32_t* pos, int cnt,
+                             int n, OpMap m, void* out, bool fp64,
+                             hipStream_t s);
 hipError_t launch_bsr_to_dense(const float* val, const BsrIndex& idx, int nb,
-                               int n, void* D, int64_t ldd, bool fp64,
+                               int n, OpMap m, void* D, int64_t ldd, bool fp64,
                                hipStream_t s);
 
 int kernel_config_count();

@@ -404,7 +404,11 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
                         SrcComb{v.w, qp, alpha, 1.0}, rowv);
       }
       __syncthreads();
-      if (threadIdx.x < kSpecRows) v.y[ch.y + threadIdx.x] = rowv[threadIdx.x];
+      // the buffer holds Y = a X~ + c I (OpMap): X~ u = (Y u - c u) / a
+      if (threadIdx.x < kSpecRows) {
+        const OpMap m = op_map(in.prm.method, in.st->p[iter], in.st->alpha[iter]);
+        v.y[ch.y + threadIdx.x] = (rowv[threadIdx.x] - m.c * u) / m.a;
+      }
     }
     grid.sync();
 
@@ -459,8 +463,10 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
       if (threadIdx.x < kSpecRows) {
         const int row = ch.y + threadIdx.x;
         const double q = v.q[pj * ldq + row] * inv;
-        const double x =
-            v.y[row] * inv - rowv[threadIdx.x] - beta * v.q[pp * ldq + row];
+        // X~ (X~ q_j) from Y (X~ q_j) = rowv (see P1)
+        const OpMap m = op_map(in.prm.method, in.st->p[iter], in.st->alpha[iter]);
+        const double xxq = (rowv[threadIdx.x] - m.c * v.y[row] * inv) / m.a;
+        const double x = v.y[row] * inv - xxq - beta * v.q[pp * ldq + row];
         v.q[pj * ldq + row] = q;
         v.w[row] = x;
         qw = q * x;

@@ -9,6 +9,10 @@
 //   X_new = S or 2 X_old - S  (Alg. 2, polynomial p_i read from device state)
 //   |X_new| < tau -> 0        (truncation E_i, sec. 5; compared in FP64)
 //   Tr X_new and sum X_new^2  (FP64; traces for the next polynomial choice)
+// With a stretch (SP2-ACC, McW-ACC) X_old is the stretched matrix
+// Y = a X~ + c I that the step squares (OpMap), d is formed from Y and S
+// with the step's coefficients, and the stored output is the next step's
+// stretched matrix.
 // Off-diagonal tiles count twice in the sums. In diagonal tiles only the
 // upper triangle (row <= col) is used and mirrored, so every iterate is
 // exactly symmetric.
@@ -78,14 +82,21 @@ __device__ __forceinline__ void store_partials(Sums s, double* part, int slot,
   }
 }
 
-// Step polynomial in the storage type. mode 0 (SP2 step): X_i = ca S +
-// cb X~ + cc I from the square S. mode 1 (McWeeny, first product): the
-// square itself is the output. mode 2 (McWeeny, second product T = X~ S):
-// X_i = ca T + cs S + cb X~ + cc I.
+// Step polynomial in the storage type, applied to the stored matrix Y of
+// the step and its square S = Y^2. mode 0 (SP2 step): X_i = ca S + cb Y,
+// i.e. S (p = 1) or 2 Y - S (p = 0). mode 1 (McWeeny, first product): the
+// square itself is the output. mode 2 (McWeeny, second product T = Y S):
+// X_i = ca T + cs S = 3 S - 2 T. e holds the FP64 error coefficients and the
+// map of the next step's matrix (StepCoef).
 template <typename T>
 struct Coef {
-  T ca, cb, cc, cs;
+  T ca, cb, cs;
   int mode;
+  // the run stretches: the error and the stored output take the step's
+  // coefficients, read from ec (ey, es, ei, an, cn) where they are used, so
+  // that they occupy no registers during the main loop; else a = 1, c = 0
+  bool affine;
+  const double* ec;
 };
 
 __device__ __forceinline__ double fused(double a, double b, double c) {
@@ -98,26 +109,30 @@ __device__ __forceinline__ float fused(float a, float b, float c) {
 // The per-element part of the epilogue. w is the multiplicity of the element
 // in the full symmetric matrix (2 off the diagonal, 1 on it); on_diag marks
 // a diagonal element of the matrix proper (not of its zero padding, which
-// must stay zero under the identity term). With the
-// coefficients of Alg. 2 (1, 0, 0) and (-1, 2, 0) the new value is exactly S
-// and the single rounding of 2 X~ - S.
+// must stay zero under the identity terms). Without a stretch the new value
+// is exactly S or the single rounding of 2 Y - S, and d = Y - S rounded once
+// in FP64. The traces are those of X~_i; the returned (stored) value is the
+// next step's matrix an X~_i + cn I, formed in FP64 and rounded once.
 template <typename T, int MODE>
 __device__ __forceinline__ T epilogue_elem(T s, T xo, T sv, const Coef<T>& k,
                                            double tau, double w, bool on_diag,
                                            Sums& acc, double& d2) {
   T xn;
   if (MODE == 2) {
-    // s = (X~ S)_ij, sv = S_ij: the new iterate, no error term
+    // s = (Y S)_ij, sv = S_ij: the new iterate, no error term
     d2 = 0.0;
-    xn = fused(k.ca, s, fused(k.cs, sv, k.cb * xo));
+    xn = fused(k.ca, s, k.cs * sv);
   } else {
-    const double d = static_cast<double>(xo) - static_cast<double>(s);
+    const double d =
+        k.affine ? __builtin_fma(k.ec[1], static_cast<double>(s),
+                                 k.ec[0] * static_cast<double>(xo)) +
+                       (on_diag ? k.ec[2] : 0.0)
+                 : static_cast<double>(xo) - static_cast<double>(s);
     d2 = d * d;
     acc.v += w * d2;
     if (MODE == 1) return s;   // the square S, kept as it is
     xn = fused(k.cb, xo, k.ca * s);
   }
-  if (on_diag) xn += k.cc;
   double xd = static_cast<double>(xn);
   if (fabs(xd) < tau) {
     xn = T(0);
@@ -125,6 +140,8 @@ __device__ __forceinline__ T epilogue_elem(T s, T xo, T sv, const Coef<T>& k,
   }
   acc.t2 += w * (xd * xd);
   if (on_diag) acc.t1 += xd;
+  if (k.affine)
+    xn = static_cast<T>(__builtin_fma(k.ec[3], xd, on_diag ? k.ec[4] : 0.0));
   return xn;
 }
 
@@ -236,7 +253,11 @@ struct StepCtx {
   bool mirror32;  // write the FP32 output's lower triangle
 };
 
-template <typename T>
+// STRETCH: the run stretches the matrices it squares (SP2-ACC, McW-ACC), so
+// the error and the stored output take the coefficients the finalize kernel
+// wrote; otherwise they are the constants of a = 1, c = 0 (the kernels of
+// Alg. 2 carry no code for a stretch).
+template <typename T, bool STRETCH>
 __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
                                                const Instance& in, int slot) {
   StepCtx<T> c;
@@ -251,17 +272,17 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const SquareArgs& a,
   c.nbk = in.nbk;
   c.mirror32 = a.mirror32 != 0;
   c.Sr = nullptr;
+  // the step's error coefficients and the map of the matrix it stores, as
+  // the finalize kernel computed them with the step's polynomial
+  const double* ec = STRETCH ? in.st->ecoef : nullptr;
   if (a.mode == 0) {
-    const StepCoef sc = step_coef(in.st->p[a.iter], in.st->alpha[a.iter]);
-    c.k = Coef<T>{static_cast<T>(sc.ca), static_cast<T>(sc.cb),
-                  static_cast<T>(sc.cc), T(0), 0};
+    const bool p1 = in.st->p[a.iter] != 0;
+    c.k = Coef<T>{p1 ? T(1) : T(-1), p1 ? T(0) : T(2), T(0), 0, STRETCH, ec};
   } else if (a.mode == 1) {
-    c.k = Coef<T>{T(1), T(0), T(0), T(0), 1};
+    c.k = Coef<T>{T(1), T(0), T(0), 1, STRETCH, ec};
     c.tau = 0.0;   // S is not an iterate: no truncation
   } else {
-    const MwCoef mc = mw_coef(in.st->alpha[a.iter]);
-    c.k = Coef<T>{static_cast<T>(mc.c3), static_cast<T>(mc.c1),
-                  static_cast<T>(mc.c0), static_cast<T>(mc.c2), 2};
+    c.k = Coef<T>{T(-2), T(0), T(3), 2, STRETCH, ec};
     c.blk = nullptr;   // the block norms came from the square
   }
   // operands: X~ X~ for a square, X~ S for McWeeny's second product
@@ -1218,7 +1239,7 @@ struct MinWaves<CfgF64<128, 2, 4, 16>> {
   static constexpr int value = 4;
 };
 
-template <class C, int MODE>
+template <class C, int MODE, bool STRETCH>
 __global__ __launch_bounds__(C::THREADS, MinWaves<C>::value) void square_kernel(
     SquareArgs a) {
   __shared__ __attribute__((aligned(16))) char smem[Ops<C>::kSmem];
@@ -1227,7 +1248,7 @@ __global__ __launch_bounds__(C::THREADS, MinWaves<C>::value) void square_kernel(
   const Instance& in = a.inst[w.inst];
   if (in.st->done) return;
   using T = typename C::T;
-  const StepCtx<T> sc = step_ctx<T>(a, in, w.slot);
+  const StepCtx<T> sc = step_ctx<T, STRETCH>(a, in, w.slot);
   typename C::Acc acc;
   Ops<C>::main(sc, w, acc, smem);
   if (w.piece < 0) {
@@ -1244,7 +1265,7 @@ __global__ __launch_bounds__(C::THREADS, MinWaves<C>::value) void square_kernel(
 // 32-element row segments) its mirror, and the band's partial sums. The last
 // band of a tile to finish (agent-scope counter) adds the bands' partials in
 // band order into the tile's slot and resets the counter: deterministic.
-template <class C, int MODE>
+template <class C, int MODE, bool STRETCH>
 __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   using T = typename C::T;
   constexpr int BM = C::BM, NBAND = BM / kMixedBlock, R = C::THREADS / BM;
@@ -1258,7 +1279,7 @@ __global__ __launch_bounds__(C::THREADS) void square_tail_kernel(SquareArgs a) {
   const TailItem t = a.tails[ti];
   const Instance& in = a.inst[t.inst];
   if (in.st->done) return;
-  const StepCtx<T> sc = step_ctx<T>(a, in, t.slot);
+  const StepCtx<T> sc = step_ctx<T, STRETCH>(a, in, t.slot);
   const int I = sc.tile.x, J = sc.tile.y;
   const bool diag = (I == J);
   const int ld = sc.ld;
@@ -1397,26 +1418,31 @@ using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
 using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
 using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
 
-template <class C, int MODE>
+template <class C, int MODE, bool STRETCH>
 hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((square_kernel<C, MODE>), dim3(grid), dim3(C::THREADS), 0,
-                     s, a);
+  hipLaunchKernelGGL((square_kernel<C, MODE, STRETCH>), dim3(grid),
+                     dim3(C::THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.ntail == 0) return e;
-  hipLaunchKernelGGL((square_tail_kernel<C, MODE>),
+  hipLaunchKernelGGL((square_tail_kernel<C, MODE, STRETCH>),
                      dim3(a.ntail * (C::BM / kMixedBlock)), dim3(C::THREADS), 0,
                      s, a);
   return hipGetLastError();
 }
 
-// The step's mode is a template parameter of the kernels, so that the SP2
-// step carries no code of the McWeeny products.
+// The step's mode and whether the run stretches are template parameters of
+// the kernels, so that the SP2 step carries no code of the McWeeny products
+// and Alg. 2 none of the stretch.
 template <class C>
 hipError_t launch_cfg(const SquareArgs& a, int grid, hipStream_t s) {
-  switch (a.mode) {
-    case 0: return launch_mode<C, 0>(a, grid, s);
-    case 1: return launch_mode<C, 1>(a, grid, s);
-    case 2: return launch_mode<C, 2>(a, grid, s);
+  const int sel = a.mode + (a.stretch ? 3 : 0);
+  switch (sel) {
+    case 0: return launch_mode<C, 0, false>(a, grid, s);
+    case 1: return launch_mode<C, 1, false>(a, grid, s);
+    case 2: return launch_mode<C, 2, false>(a, grid, s);
+    case 3: return launch_mode<C, 0, true>(a, grid, s);
+    case 4: return launch_mode<C, 1, true>(a, grid, s);
+    case 5: return launch_mode<C, 2, true>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

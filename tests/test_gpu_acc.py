@@ -57,8 +57,9 @@ def _run(inst, bounds, accelerate=True, **kw):
 def test_acc_first_step_elementwise(prec, cfg, n, split):
     """X~_1 = ((1 - a) I + a X~_0)^2 with a stretch a > 1.3, element by
     element against the FP64 oracle, for every kernel configuration: the
-    expanded epilogue a^2 S + 2a(1 - a) X~ + (1 - a)^2 I is right in every
-    tile, on the diagonal and off it, and in the ragged tail."""
+    stretched matrix Y = a X~_0 + (1 - a) I that the affine start stores is
+    right in every tile, on the diagonal and off it, and in the ragged tail,
+    and the step squares it."""
     inst = dense_instance(n, n // 2, -1.0, 1.3, 0.1, seed=2000 + n)
     b = _exact_bounds(inst)
     sched = oracle.acc_schedule(inst.lambda_min, inst.lambda_max, *b)
@@ -71,11 +72,12 @@ def test_acc_first_step_elementwise(prec, cfg, n, split):
     assert res.p[1] == 1
     D = res.D.cpu().numpy()
     a = sched.alpha[1]
-    # S within the square bound (plus the storage rounding of X~_0 carried
-    # through the square), scaled by a^2; the three-term combination adds a
-    # few roundings of O(a^2) terms
+    # Y = a X~_0 + (1 - a) I carries the storage rounding of X~_0 (scaled by
+    # a) and its own; rows of Y have norm <= 1, so that rounding moves an
+    # entry of Y^2 by at most 2 sqrt(n) (a + 1) u; the square itself is
+    # within the square bound, and X~_1 is rounded once more
     u = U_STORE[prec]
-    tol = a * a * (square_bound(n, prec) + 4 * u) + 8 * a * a * u
+    tol = square_bound(n, prec) + 2 * math.sqrt(n) * (a + 1) * u + 2 * u
     err = float(np.max(np.abs(D - ref.X)))
     assert err <= tol, (err, tol)
     assert np.array_equal(D, D.T)
@@ -109,18 +111,19 @@ def test_acc_full_run(prec):
         assert res.r[res.n] < 1.8
     if prec == "fp64":
         assert abs(res.n - ref.n) <= 2
-    # History against the oracle while the error is well above rounding. The
-    # GPU forms a stretched x^2 step as a^2 S + 2a(1 - a) X~ + (1 - a)^2 I
-    # from S = X~^2, so the square's rounding enters scaled by a^2 where the
-    # oracle squares (1 - a) I + a X~ (norm <= 1): allow 100 (k + 1) u_eff
-    # times the product of a_j^2 up to step k.
+    # History against the oracle while the error is well above rounding: the
+    # GPU squares the stretched matrix like the oracle, so the relative
+    # deviation stays within 100 (k + 1) u_eff (u_eff the working
+    # precision's unit roundoff; bf16x3 carries 16 significant bits), capped
+    # at 1e-2.
     u_eff = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
-    amp = 1.0
+    worst = 0.0
     for k, (x, y) in enumerate(zip(res.v, ref.v)):
-        if k:
-            amp *= sched.alpha[k] ** 2 if k <= sched.n_max else 1.0
         if y > 1e-3:
-            assert abs(x - y) <= 100 * (k + 1) * u_eff * amp * y + 1e-13, (k, x, y)
+            bound = min(100 * (k + 1) * u_eff, 1e-2)
+            worst = max(worst, abs(x - y) / y)
+            assert abs(x - y) <= bound * y + 1e-13, (k, x, y, bound)
+    print_case(f"  worst relative history deviation {worst:.2e}")
     plain = sp2.run_dense(res.D.new_tensor(inst.F), inst.lambda_min, inst.lambda_max,
                           inst.n_occ, precision=prec)
     assert res.n_squares < plain.n_squares

@@ -55,8 +55,9 @@ def _run(inst, xi=None, **kw):
 @pytest.mark.parametrize("acc", [False, True])
 def test_one_step_elementwise(prec, cfg, n, split, acc):
     """X~_1 of one McWeeny (or McW-ACC) step, element by element, for every
-    configuration: the square's output S, the product X~ S with S as the
-    second operand, and the combination c3 T + c2 S + c1 X~ + c0 I."""
+    configuration: the stretched matrix X_s = a (X~_0 - I/2) + I/2 the affine
+    start stores, the square's output S = X_s^2, the product T = X_s S with S
+    as the second operand, and 3 S - 2 T."""
     inst = dense_instance(n, n // 2, -1.0, 1.3, 0.1, seed=1000 + n)
     xi = _gap(inst) if acc else None
     print_case(f"mcweeny one step n={n} prec={prec} cfg={cfg} split={split} acc={acc}")
@@ -65,14 +66,14 @@ def test_one_step_elementwise(prec, cfg, n, split, acc):
     assert res.status_name == "NOT_CONVERGED" and res.n == 1
     assert ref.status == Status.NOT_CONVERGED
     a = ref.p[1]
-    b = 0.5 * (1 - a)
-    # |c3|, |c2|, |c1|, |c0| of the expanded step
-    coef = (2 * a ** 3, abs(3 * a * a - 6 * a * a * b), abs(6 * a * b - 6 * a * b * b),
-            abs(3 * b * b - 2 * b ** 3))
     u = U64 if prec == "fp64" else U32
-    eps_s = square_bound(n, prec) + 4 * u          # S, with X~_0's storage rounding
-    eps_t = (math.sqrt(n) + 1) * eps_s             # T = X~ S carries S's error
-    tol = coef[0] * eps_t + coef[1] * eps_s + 16 * u * sum(coef)
+    # X_s carries the storage rounding of X~_0 (scaled by a) and its own;
+    # rows of X_s have norm <= 1, so S = X_s^2 is within the square bound
+    # plus 2 sqrt(n) (a + 1) u, T = X_s S carries S's error, and
+    # 3 S - 2 T adds a few roundings
+    eps_s = square_bound(n, prec) + 2 * math.sqrt(n) * (a + 1) * u + 2 * u
+    eps_t = (math.sqrt(n) + 1) * eps_s
+    tol = 3 * eps_s + 2 * eps_t + 16 * u
     D = res.D.cpu().numpy()
     err = float(np.max(np.abs(D - ref.X)))
     assert err <= tol, (err, tol)
@@ -102,13 +103,16 @@ def test_full_run(prec, acc):
     assert r < 1.8 and res.r[k] == pytest.approx(r, rel=1e-12)
     if prec == "fp64":
         assert abs(res.n - ref.n) <= 2
+    # the GPU squares the stretched matrix X_s like the oracle: the relative
+    # deviation of the history stays within 100 (j + 1) u_eff, capped at 1e-2
     u_eff = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24, "bf16x3": 2.0 ** -16}[prec]
-    amp = 1.0
+    worst = 0.0
     for j, (x, y) in enumerate(zip(res.v, ref.v)):
-        if j:
-            amp *= max(1.0, 2 * ref.p[j] ** 3) if j < len(ref.p) else 1.0
         if y > 1e-3:
-            assert abs(x - y) <= 100 * (j + 1) * u_eff * amp * y + 1e-13, (j, x, y)
+            bound = min(100 * (j + 1) * u_eff, 1e-2)
+            worst = max(worst, abs(x - y) / y)
+            assert abs(x - y) <= bound * y + 1e-13, (j, x, y, bound)
+    print_case(f"  worst relative history deviation {worst:.2e}")
 
 
 def test_ragged_padding():
