@@ -68,6 +68,20 @@ def square_flops(n: int) -> float:
     return float(n) * n * (n + 1)
 
 
+def cpu_info():
+    """Model name and logical CPU count of this host (from /proc/cpuinfo)."""
+    model, count = None, 0
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    count += 1
+                    model = model or line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": count or os.cpu_count()}
+
+
 def cpu_baseline(inst, squares_needed: int, sample_squares: int):
     """Times the FP64 oracle on its first `sample_squares` squares of the
     same input and scales per-square time to the GPU FP64 square count."""
@@ -90,11 +104,11 @@ def cpu_baseline(inst, squares_needed: int, sample_squares: int):
     est_ms = per_square * squares_needed * 1e3
     return {
         "value": round(est_ms, 1), "unit": "ms", "cores": threads,
-        "kind": "oracle",
+        "kind": "oracle", "extrapolated": True,
         "sample": (f"FP64 NumPy oracle, first {res.n_squares} squares of the same "
                    f"N={inst.n} input in {dt:.2f} s ({per_square:.3f} s/square), "
                    f"scaled to the {squares_needed} squares of the GPU FP64 run"),
-        "per_square_s": round(per_square, 4),
+        "per_square_s": round(per_square, 4), **cpu_info(),
     }
 
 
@@ -185,24 +199,11 @@ def bench_batch(args):
                      "per_run_flops": flops},
         "cpu_baseline": {"value": round(cpu_ms_est, 1), "unit": "ms",
                          "cores": blas_threads(), "kind": "oracle",
+                         "extrapolated": True,
                          "sample": f"FP64 oracle on the first {cnt} instances "
                                    f"({cpu_s:.1f} s), scaled by algorithmic flops "
-                                   "to the whole batch"},
+                                   "to the whole batch", **cpu_info()},
     }
-
-
-def cpu_info():
-    """Model name and logical CPU count of this host (from /proc/cpuinfo)."""
-    model, count = None, 0
-    try:
-        with open("/proc/cpuinfo") as fh:
-            for line in fh:
-                if line.startswith("model name"):
-                    count += 1
-                    model = model or line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return {"cpu_model": model, "logical_cpus": count or os.cpu_count()}
 
 
 BAND_GOLDEN = os.path.join(ROOT, "tests", "golden", "band_n32768.json")

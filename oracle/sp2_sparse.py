@@ -63,10 +63,13 @@ def mixed_norm_csr(A: sps.spmatrix, block: int = 32) -> float:
 
 def sp2_csr(F: sps.spmatrix, lambda_min: float, lambda_max: float, n_occ: int,
             tau: float = 0.0, branch: str = "nearest", max_iter: int = 100,
-            norm: str = "fro", mixed_block: int = 32) -> SP2Result:
+            norm: str = "fro", mixed_block: int = 32,
+            perturb=None) -> SP2Result:
     """Alg. 2 (original SP2 with the new stopping criterion) on CSR matrices
     in FP64; arguments and result as ``oracle.sp2.sp2`` (res.X is CSR).
-    norm: "fro" (R1) or "mixed" (block edge ``mixed_block``)."""
+    norm: "fro" (R1) or "mixed" (block edge ``mixed_block``). ``perturb(i, X)``
+    returns a sparse E_i added after the truncation of X~_i (the experiments
+    of sec. 4.1 and sec. 5 perturb every iterate)."""
     F = sps.csr_matrix(F, dtype=np.float64)
     if F.ndim != 2 or F.shape[0] != F.shape[1] or F.shape[0] == 0:
         return SP2Result(None, 0, Status.INVALID_ARG)
@@ -85,6 +88,8 @@ def sp2_csr(F: sps.spmatrix, lambda_min: float, lambda_max: float, n_occ: int,
         return fro_csr(A) if norm == "fro" else mixed_norm_csr(A, mixed_block)
 
     X = truncate_csr(f0_csr(F, lambda_min, lambda_max), tau)   # X~_0
+    if perturb is not None:
+        X = (X + perturb(0, X)).tocsr()
     res = SP2Result(None, 0, Status.NOT_CONVERGED)
     res.p.append(-1)
     res.t1.append(float(X.diagonal().sum()))
@@ -113,6 +118,8 @@ def sp2_csr(F: sps.spmatrix, lambda_min: float, lambda_max: float, n_occ: int,
         res.p.append(pi)
         Xi = S if pi == 1 else (2.0 * X - S).tocsr()   # Alg. 2, X_i
         X = truncate_csr(Xi, tau)                      # X~_i = X_i + E_i
+        if perturb is not None:
+            X = (X + perturb(i, X)).tocsr()
         t1n, t2n = float(X.diagonal().sum()), float(np.sum(X.data * X.data))
         res.t1.append(t1n)
         res.t2.append(t2n)
