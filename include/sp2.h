@@ -110,6 +110,34 @@ typedef enum {
                               the Lanczos processes of all instances */
 } sp2_norm;
 
+/* How a run is driven. */
+typedef enum {
+  SP2_LAUNCH_AUTO = 0,       /* persistent for a batch of more than one
+                                instance with the Frobenius norm (Alg. 2 or
+                                SP2-ACC), otherwise a launch sequence per
+                                step */
+  SP2_LAUNCH_SEQUENCE = 1,   /* one sequence of kernel launches per step
+                                (square kernels per configuration, then the
+                                scalar step for all instances); the host
+                                queues a few steps ahead of the last outcome
+                                it has observed */
+  SP2_LAUNCH_PERSISTENT = 2  /* one persistent kernel for the whole run,
+                                captured with the affine start in a HIP graph
+                                at the first run after an init and replayed
+                                by every later run: its workgroups take
+                                (instance, tile, step) items from a queue in
+                                device memory, the workgroup that finishes an
+                                instance's last tile of a step runs that
+                                instance's stop and branch logic and queues
+                                its next step, so every instance advances and
+                                stops on its own. Every instance uses one
+                                square-kernel configuration (kernel_config, or
+                                the library's choice for the largest
+                                instance) among the 64- and 128-tile ones;
+                                Frobenius norm only; kernel_timing records
+                                nothing */
+} sp2_launch;
+
 /* Block edge of SP2_NORM_MIXED. */
 #define SP2_MIXED_BLOCK 32
 
@@ -133,12 +161,12 @@ typedef struct {
                             sp2_get_kernel_times); adds a few microseconds
                             per step */
   int32_t norm;       /* sp2_norm: the error of the stop test */
-  int32_t reserved;   /* must be 0 */
+  int32_t launch;     /* sp2_launch: how a run is driven */
 } sp2_options;
 
 /* Fills *opt with the defaults: SP2_FP64, SP2_BRANCH_NEAREST, no truncation,
  * max_iter 100, automatic kernel configuration and tail split, no kernel
- * timing, Frobenius norm. */
+ * timing, Frobenius norm, automatic launch. */
 void sp2_default_options(sp2_options* opt);
 
 /* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OUT_OF_MEMORY", 3: "HIP_ERROR",
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 BRANCHES = {"nearest": 0, "literal": 1}
 NORMS = {"fro": 0, "mixed": 1, "spectral": 2}
+LAUNCHES = {"auto": 0, "sequence": 1, "persistent": 2}
 MIXED_BLOCK = 32
 MAX_ITER_LIMIT = 200
 
@@ -102,7 +103,7 @@ class Options(ctypes.Structure):
                 ("trunc_tau", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("kernel_config", ctypes.c_int32), ("tail_split", ctypes.c_int32),
                 ("kernel_timing", ctypes.c_int32), ("norm", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("launch", ctypes.c_int32)]
 
 
 _lib = None
@@ -244,7 +245,8 @@ class Context:
                    precision: str = "fp64", branch: str = "nearest",
                    trunc_tau: float = 0.0, max_iter: int = 100,
                    kernel_config: int = 0, tail_split: int = 0,
-                   kernel_timing: bool = False, norm: str = "fro"):
+                   kernel_timing: bool = False, norm: str = "fro",
+                   launch: str = "auto"):
         import torch
         if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
             raise TypeError("F must be a float64 CUDA tensor")
@@ -252,7 +254,7 @@ class Context:
             raise ValueError("F must be square with unit column stride")
         opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
                       int(max_iter), int(kernel_config), int(tail_split),
-                      1 if kernel_timing else 0, NORMS[norm], 0)
+                      1 if kernel_timing else 0, NORMS[norm], LAUNCHES[launch])
         self._F = F   # keep alive until run() returns
         st = self._lib.sp2_init_dense(self._h, ctypes.c_void_p(F.data_ptr()),
                                       F.shape[0], F.stride(0), float(lambda_min),
@@ -461,7 +463,7 @@ class BatchContext(Context):
     def batch_init(self, Fs, lambda_min, lambda_max, n_occ, precision: str = "fp64",
                    branch: str = "nearest", trunc_tau: float = 0.0,
                    max_iter: int = 100, kernel_config: int = 0, tail_split: int = 0,
-                   kernel_timing: bool = False, norm: str = "fro"):
+                   kernel_timing: bool = False, norm: str = "fro", launch: str = "auto"):
         import torch
         for F in Fs:
             if not (isinstance(F, torch.Tensor) and F.is_cuda and F.dtype == torch.float64):
@@ -471,7 +473,7 @@ class BatchContext(Context):
         cnt = len(Fs)
         opt = Options(PRECISIONS[precision], BRANCHES[branch], float(trunc_tau),
                       int(max_iter), int(kernel_config), int(tail_split),
-                      1 if kernel_timing else 0, NORMS[norm], 0)
+                      1 if kernel_timing else 0, NORMS[norm], LAUNCHES[launch])
         self._Fs = list(Fs)   # keep alive until batch_run() returns
         ptrs = _arr(ctypes.c_void_p, [F.data_ptr() for F in Fs])
         ns = _arr(ctypes.c_int64, [F.shape[0] for F in Fs])
@@ -558,7 +560,7 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
               kernel_config: int = 0, tail_split: int = 0,
               as_fp64: bool = True, ctx: Context | None = None,
               homo_lumo=None, accelerate: bool = True, norm: str = "fro",
-              mcweeny=None) -> Result:
+              mcweeny=None, launch: str = "auto") -> Result:
     """SP2 (Alg. 2) on the GPU from F to the converged density matrix; with
     homo_lumo = (homo_out, homo_in, lumo_in, lumo_out), SP2-ACC (Alg. 3/4);
     with mcweeny = (mu, xi or None), McWeeny / McW-ACC (sec. 3)."""
@@ -567,7 +569,8 @@ def run_dense(F, lambda_min: float, lambda_max: float, n_occ: int,
         ctx = Context(F.device.index or 0)
     try:
         ctx.init_dense(F, lambda_min, lambda_max, n_occ, precision, branch,
-                       trunc_tau, max_iter, kernel_config, tail_split, norm=norm)
+                       trunc_tau, max_iter, kernel_config, tail_split, norm=norm,
+                       launch=launch)
         if homo_lumo is not None:
             ctx.set_homo_lumo(*homo_lumo, accelerate=accelerate)
         if mcweeny is not None:

@@ -2,6 +2,7 @@
 // traces, the scalar finalize/stop step, and small fill/copy kernels.
 #include <math.h>
 
+#include "finalize_logic.h"
 #include "sp2_device.h"
 #include "tridiag.h"
 
@@ -11,15 +12,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// C of Alg. 2: the smallest constant with r_k >= 2 in exact arithmetic over
-// two alternating SP2 steps, (71 + 17 sqrt 17) / 32.
-__device__ __forceinline__ double c_sp2() {
-  return (71.0 + 17.0 * sqrt(17.0)) / 32.0;
-}
-// q~ of sec. 2.
-constexpr double kQTilde = 1.8;
-// sec. 3: C_2 of the McWeeny and McW-ACC expansions.
-constexpr double kCMcWeeny = 4.0;
 
 __device__ __forceinline__ double wave_sum(double x) {
   for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -231,19 +223,6 @@ __device__ double mixed_norm(const Instance& in, int iter, double* w,
   return theta;
 }
 
-__device__ __forceinline__ void publish(DevState* st, int32_t* ndone,
-                                        int count, HostMirror* m, int status,
-                                        int n) {
-  st->status = status;
-  st->n = n;
-  st->done = 1;
-  __threadfence();
-  const int before = atomicAdd(ndone, 1);
-  if (before == count - 1 && m)
-    __hip_atomic_store(&m->all_done, 1, __ATOMIC_RELEASE,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 // One block per instance: sums the instance's partial triples of step
 // `iter` in a fixed order and applies the scalar part of Alg. 2 (Alg. 4
 // with a schedule) on one thread:
@@ -280,118 +259,7 @@ __global__ __launch_bounds__(kThreads) void finalize_kernel(
     mk = mixed_norm(in, iter, wv, cf, ta, tb, hits, red, &mk_steps);
   }
   if (threadIdx.x != 0) return;
-
-  const bool sched = prm.n_max > 0;
-  const bool mw = (prm.method == 1);
-  const double t1 = b, t2 = c;
-  st->t1[iter] = t1;
-  st->t2[iter] = t2;
-  if (iter == 0) {
-    if (prm.n_occ == 0.0 || prm.n_occ == prm.n) {
-      publish(st, ndone, count, mirror, /*OK*/ 0, 0);
-      return;
-    }
-    if (!isfinite(t1) || !isfinite(t2)) {
-      publish(st, ndone, count, mirror, /*DIVERGED*/ 5, 0);
-      return;
-    }
-  } else {
-    const int k = iter - 1;
-    const double vk = sqrt(a);
-    st->v[k] = vk;
-    if (prm.norm == 1) {   // the spectral kernel writes m[k] itself
-      st->m[k] = mk;
-      st->krylov[k] = mk_steps;
-    }
-    st->squares = iter;
-    // the error the stop test reads: Frobenius, mixed or spectral (sec. 2)
-    const double* e = (prm.norm != 0) ? st->m : st->v;
-    const double ek = e[k];
-    double r = NAN;
-    if (mw) {
-      // McWeeny: one polynomial per step, C = 4 (sec. 3)
-      if (k >= 1) {
-        const double ekm1 = e[k - 1];
-        if (ekm1 > 0.0 && ekm1 < 1.0 && ek > 0.0)
-          r = log(ek / kCMcWeeny) / log(ekm1);
-      }
-    } else if (k >= 2) {
-      const double ekm2 = e[k - 2];
-      if (ekm2 > 0.0 && ekm2 < 1.0 && ek > 0.0)
-        r = log(ek / c_sp2()) / log(ekm2);   // observed order (sec. 2)
-    }
-    st->r[k] = r;
-    if (!isfinite(vk)) {
-      publish(st, ndone, count, mirror, 5, k);
-      return;
-    }
-    if (vk == 0.0) {                          // exactly idempotent
-      publish(st, ndone, count, mirror, 0, k);
-      return;
-    }
-    if (mw) {
-      if (k >= prm.mw_first && !isnan(r) && r < kQTilde) {
-        publish(st, ndone, count, mirror, 0, k);   // McWeeny stop (sec. 3)
-        return;
-      }
-    } else {
-      const int kmin = sched ? prm.n_min : 2;
-      if (k >= kmin && st->p[k] != st->p[k - 1] && !isnan(r) && r < kQTilde) {
-        publish(st, ndone, count, mirror, 0, k);   // Alg. 2 / Alg. 4 stop
-        return;
-      }
-    }
-    if (sched && k >= prm.n_max) {               // the schedule has ended
-      publish(st, ndone, count, mirror, 0, k);
-      return;
-    }
-    if (!isfinite(t1) || !isfinite(t2) || t2 > t1 + prm.n) {
-      publish(st, ndone, count, mirror, 5, iter);
-      return;
-    }
-    if (iter >= prm.max_iter) {
-      publish(st, ndone, count, mirror, /*NOT_CONVERGED*/ 4, iter);
-      return;
-    }
-  }
-  // Polynomial of the next step: from the schedule (Alg. 4), or from the
-  // traces of X~_iter (Alg. 2 branch). Past the schedule's end one more
-  // square is needed for v_{n_max}; the iterate it yields is not used.
-  // McWeeny: one polynomial; the stretch of McW-ACC from the host's table
-  // (computed from the beta recursion at set-up, switched off once
-  // beta < 0.01 with the Frobenius or the mixed norm).
-  int pn;
-  double an = 1.0;
-  if (mw) {
-    const int i = iter + 1;
-    pn = 1;
-    if (i <= prm.mw_len) an = in.sched_alpha[i];
-  } else if (sched) {
-    const int i = iter + 1;
-    if (i <= prm.n_max) {
-      pn = in.sched_p[i];
-      an = in.sched_alpha[i];
-    } else {
-      pn = 1 - st->p[iter];
-    }
-  } else if (prm.branch == 1) {
-    pn = (t1 > prm.n_occ) ? 1 : 0;
-  } else {
-    pn = (fabs(t2 - prm.n_occ) < fabs(2.0 * t1 - t2 - prm.n_occ)) ? 1 : 0;
-  }
-  st->p[iter + 1] = static_cast<int8_t>(pn);
-  st->alpha[iter + 1] = an;
-  // epilogue coefficients of step iter + 1: the error of X~_iter from the
-  // stored matrix of that step and its square, and the map of the matrix
-  // it stores for step iter + 2
-  const OpMap nxt = step_map(in, iter + 2);
-  const StepCoef e = step_coef(op_map(prm.method, pn, an), nxt);
-  st->ecoef[0] = e.ey;
-  st->ecoef[1] = e.es;
-  st->ecoef[2] = e.ei;
-  st->ecoef[3] = e.an;
-  st->ecoef[4] = e.cn;
-  st->stretch = (nxt.a != 1.0 || nxt.c != 0.0) ? 1 : 0;
+  finalize_scalar(in, iter, a, b, c, mk, mk_steps, ndone, count, mirror);
 }
 
 // D = (X - c I) / a (OpMap m; a = 1, c = 0 copies exactly).

@@ -14,6 +14,7 @@
 // because every kernel first reads its instance's done flag.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -167,6 +168,24 @@ struct sp2_ctx_s {
     size_t bytes = 0;              // bytes of the allocation below
     void* mem = nullptr;           // one allocation holding all of the above
   } b;
+
+  // persistent driver (SP2_LAUNCH_PERSISTENT): the configuration every
+  // instance uses, the queue, and the captured graph of a run
+  bool persistent = false;
+  int pcfg = 0;
+  int pgrid = 0;
+  sp2::PItem* d_pitems = nullptr;
+  size_t d_pitems_cap = 0;
+  int32_t pitems = 0;
+  int32_t* d_pctl = nullptr;       // 4 counters
+  size_t d_pctl_cap = 0;
+  int32_t* d_pcnt = nullptr;       // per instance
+  size_t d_pcnt_cap = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  long long wall_khz = 100000;     // rate of the kernels' constant clock
+  long long wait_ms = 2000;        // longest wait of a workgroup for an item
 
   // Workspace arena of the no-allocation entry point (null for contexts made
   // by sp2_create): every workspace is carved from it instead of allocated.
@@ -354,8 +373,11 @@ sp2_status validate_options(sp2_ctx c, sp2_options& opt) {
   if (opt.norm != SP2_NORM_FROBENIUS && opt.norm != SP2_NORM_MIXED &&
       opt.norm != SP2_NORM_SPECTRAL)
     return fail(c, SP2_INVALID_ARG, "unknown norm", hipSuccess);
-  if (opt.reserved != 0)
-    return fail(c, SP2_INVALID_ARG, "reserved option field must be 0",
+  if (opt.launch < SP2_LAUNCH_AUTO || opt.launch > SP2_LAUNCH_PERSISTENT)
+    return fail(c, SP2_INVALID_ARG, "unknown launch mode", hipSuccess);
+  if (opt.launch == SP2_LAUNCH_PERSISTENT && opt.norm != SP2_NORM_FROBENIUS)
+    return fail(c, SP2_INVALID_ARG,
+                "the persistent launch supports the Frobenius norm only",
                 hipSuccess);
   return SP2_OK;
 }
@@ -376,6 +398,15 @@ sp2_status validate_instance(sp2_ctx c, const double* F, int64_t n, int64_t ldf,
   return SP2_OK;
 }
 
+// Drops the captured run of the persistent driver (its kernel arguments
+// name workspaces that a new init may replace).
+void release_graph(sp2_ctx c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+}
+
 void release_groups(sp2_ctx c) {
   for (Group& g : c->groups) {
     if (c->arena) continue;   // carved from the arena
@@ -391,17 +422,42 @@ sp2_status setup(sp2_ctx c) {
   const int count = static_cast<int>(c->hi.size());
   const size_t esz = c->fp64_store ? 8 : 4;
   hipStream_t s = c->stream;
+  release_graph(c);
   // configurations, padding, pool offsets
-  size_t pool_elems = 0;
-  for (HostInst& h : c->hi) {
-    h.cfg = c->opt.kernel_config ? c->opt.kernel_config - 1
-                                 : default_config(c->opt.precision, h.n);
+  auto choose = [&](int64_t n) {
+    int cfg = c->opt.kernel_config ? c->opt.kernel_config - 1
+                                   : default_config(c->opt.precision, n);
     if (!c->opt.kernel_config)
       for (const auto& e : c->table)
-        if (e.precision == c->opt.precision && h.n <= e.n_max) {
-          h.cfg = e.cfg;
+        if (e.precision == c->opt.precision && n <= e.n_max) {
+          cfg = e.cfg;
           break;
         }
+    return cfg;
+  };
+  // the persistent driver runs every instance with one configuration: the
+  // choice for the largest instance when the persistent kernel is compiled
+  // for it, else the 64/128-tile default of the precision
+  c->persistent =
+      !c->arena && c->opt.norm == SP2_NORM_FROBENIUS &&
+      (c->opt.launch == SP2_LAUNCH_PERSISTENT ||
+       (c->opt.launch == SP2_LAUNCH_AUTO && count > 1));
+  if (c->persistent) {
+    int64_t nmax = 0;
+    for (const HostInst& h : c->hi) nmax = std::max(nmax, h.n);
+    int cfg = choose(nmax);
+    if (!sp2::persist_supported(cfg)) {
+      if (c->opt.kernel_config)
+        return fail(c, SP2_INVALID_ARG,
+                    "kernel_config is not one the persistent launch is "
+                    "compiled for", hipSuccess);
+      cfg = c->opt.precision == SP2_FP64 ? 2 : (c->opt.precision == SP2_FP32 ? 4 : 11);
+    }
+    c->pcfg = cfg;
+  }
+  size_t pool_elems = 0;
+  for (HostInst& h : c->hi) {
+    h.cfg = c->persistent ? c->pcfg : choose(h.n);
     const int bm = sp2::kernel_config(h.cfg)->bm;
     h.np = ((h.n + bm - 1) / bm) * bm;
     h.ld = row_stride(h.np);
@@ -607,6 +663,116 @@ sp2_status setup(sp2_ctx c) {
                             hipMemcpyHostToDevice, s));
   SP2_HIP(c, hipStreamSynchronize(s));
   c->nf0 = static_cast<int>(f0.size());
+  if (c->persistent) {
+    // every step of every instance can be queued once
+    size_t cap = 1;
+    for (int b = 0; b < count; ++b)
+      if (!c->hi[b].trivial)
+        cap += static_cast<size_t>(inst[b].ntiles) * c->opt.max_iter;
+    if (cap > static_cast<size_t>(INT32_MAX))
+      return fail(c, SP2_INVALID_ARG, "batch too large for the persistent launch",
+                  hipSuccess);
+    c->pitems = static_cast<int32_t>(cap);
+    SP2_HIP(c, grow(c, c->d_pitems, c->d_pitems_cap, cap * sizeof(sp2::PItem), s));
+    SP2_HIP(c, grow(c, c->d_pctl, c->d_pctl_cap, 4 * sizeof(int32_t), s));
+    SP2_HIP(c, grow(c, c->d_pcnt, c->d_pcnt_cap, count * sizeof(int32_t), s));
+  }
+  return SP2_OK;
+}
+
+// The persistent driver's run, captured once (after every init, and after
+// a change of the stretch) on a private stream into a graph that every run
+// launches on the context's stream: the state reset, the affine start and
+// its scalar step, the queue seeding and the persistent kernel. Errors
+// inside the capture end it before returning.
+sp2_status capture_persistent(sp2_ctx c) {
+  const int count = static_cast<int>(c->hi.size());
+  if (!c->cap_stream)
+    SP2_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  const int grid = sp2::persist_grid(c->pcfg, c->stretch, c->num_cus);
+  if (grid < 1)
+    return fail(c, SP2_HIP_ERROR, "persistent kernel: no resident workgroup",
+                hipGetLastError());
+  c->pgrid = grid;
+  sp2::SquareArgs a{};
+  a.inst = c->d_inst;
+  a.tiles = c->d_tiles;
+  a.part = c->d_part;
+  a.iter = 1;
+  a.mode = 0;
+  a.stretch = c->stretch ? 1 : 0;
+  a.split = 1;
+  a.mirror32 = sp2::kernel_config(c->pcfg)->presplit ? 0 : 1;
+  sp2::PQueue q{};
+  q.items = c->d_pitems;
+  q.cap = c->pitems;
+  q.count = count;
+  q.ctl = c->d_pctl;
+  q.cnt = c->d_pcnt;
+  q.ndone = c->d_ndone;
+  q.mirror = c->mirror;
+  q.wait_limit = c->wait_ms * c->wall_khz;
+  hipStream_t cs = c->cap_stream;
+  SP2_HIP(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hipError_t e = sp2::launch_state_reset(c->d_st, count, c->d_ndone, nullptr, 0, cs);
+  if (e == hipSuccess)
+    e = sp2::launch_f0(c->d_inst, c->d_f0, c->nf0, c->fp64_store, c->d_part_f0, cs);
+  if (e == hipSuccess)
+    e = sp2::launch_finalize(c->d_inst, count, c->d_part, c->d_part_f0,
+                             c->d_ndone, c->mirror, 0, cs);
+  if (e == hipSuccess) e = sp2::launch_persist_seed(c->d_inst, count, q, cs);
+  if (e == hipSuccess) e = sp2::launch_persist(c->pcfg, a, q, grid, cs);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(cs, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(c, SP2_HIP_ERROR, "capturing the persistent run",
+                e != hipSuccess ? e : e2);
+  }
+  c->graph = g;
+  SP2_HIP(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+  return SP2_OK;
+}
+
+// One run of the persistent driver: the captured graph on the context's
+// stream, then the outcome of every instance.
+sp2_status run_persistent(sp2_ctx c) {
+  const int count = static_cast<int>(c->hi.size());
+  hipStream_t s = c->stream;
+  if (!c->gexec) {
+    const sp2_status st = capture_persistent(c);
+    if (st != SP2_OK) return st;
+  }
+  c->mirror->all_done = 0;
+  __atomic_thread_fence(__ATOMIC_SEQ_CST);
+  c->timed = false;
+  c->square_ms.clear();
+  c->norm_ms.clear();
+  SP2_HIP(c, hipEventRecord(c->ev_start, s));
+  SP2_HIP(c, hipGraphLaunch(c->gexec, s));
+  SP2_HIP(c, hipEventRecord(c->ev_stop, s));
+  SP2_HIP(c, hipEventSynchronize(c->ev_stop));
+  float ms = 0.f;
+  SP2_HIP(c, hipEventElapsedTime(&ms, c->ev_start, c->ev_stop));
+  int32_t ctl[4] = {0, 0, 0, 0};
+  SP2_HIP(c, hipMemcpyAsync(ctl, c->d_pctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+  c->host_state.resize(count);
+  SP2_HIP(c, hipMemcpyAsync(c->host_state.data(), c->d_st,
+                            count * sizeof(DevState), hipMemcpyDeviceToHost, s));
+  SP2_HIP(c, hipStreamSynchronize(s));
+  if (ctl[2] != 0)
+    return fail(c, SP2_HIP_ERROR,
+                "persistent run: a workgroup waited for a queue item longer "
+                "than its limit", hipSuccess);
+  int32_t steps = 0;
+  for (const DevState& h : c->host_state) {
+    if (!h.done)
+      return fail(c, SP2_BAD_STATE, "run ended without an outcome", hipSuccess);
+    steps = std::max(steps, h.squares);
+  }
+  c->steps = steps;
+  c->run_ms = ms;
+  c->ran = true;
   return SP2_OK;
 }
 
@@ -616,6 +782,7 @@ constexpr int kNoAllocChunk = 4;
 
 sp2_status run_batch(sp2_ctx c) {
   SP2_HIP(c, hipSetDevice(c->device));
+  if (c->persistent && !c->mcweeny && !c->bsr) return run_persistent(c);
   hipStream_t s = c->stream;
   const int count = static_cast<int>(c->hi.size());
   const bool noalloc = (c->arena != nullptr);
@@ -904,7 +1071,7 @@ void sp2_default_options(sp2_options* opt) {
   opt->tail_split = 0;
   opt->kernel_timing = 0;
   opt->norm = SP2_NORM_FROBENIUS;
-  opt->reserved = 0;
+  opt->launch = SP2_LAUNCH_AUTO;
 }
 
 const char* sp2_status_string(sp2_status s) {
@@ -981,6 +1148,17 @@ sp2_status sp2_create(sp2_ctx* out, int device, void* hip_stream) {
     return e == hipErrorOutOfMemory ? SP2_OUT_OF_MEMORY : SP2_HIP_ERROR;
   }
   memset(c->mirror, 0, sizeof(HostMirror));
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) ==
+          hipSuccess && khz > 0)
+    c->wall_khz = khz;
+  // SP2_PERSIST_WAIT_MS: longest wait of a persistent workgroup for a queue
+  // item before the run gives up (milliseconds; default 2000)
+  if (const char* w = getenv("SP2_PERSIST_WAIT_MS")) {
+    char* end = nullptr;
+    const long long v = strtoll(w, &end, 10);
+    if (end != w && v >= 0) c->wait_ms = v;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess &&
       prop.multiProcessorCount > 0)
@@ -1023,6 +1201,11 @@ sp2_status sp2_destroy(sp2_ctx c) {
   rel(c->d_bcnt);
   rel(c->d_ndone);
   rel(c->b.mem);
+  rel(c->d_pitems);
+  rel(c->d_pctl);
+  rel(c->d_pcnt);
+  release_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   release_groups(c);
   if (c->mirror) (void)hipHostFree(c->mirror);
   if (c->ev_start) (void)hipEventDestroy(c->ev_start);
@@ -1416,6 +1599,10 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
   if (c->h_inst.size() && c->h_inst[0].prm.n_max > 0)
     return fail(c, SP2_INVALID_ARG,
                 "an SP2-ACC schedule is set: re-initialise first", hipSuccess);
+  if (c->opt.launch == SP2_LAUNCH_PERSISTENT)
+    return fail(c, SP2_INVALID_ARG,
+                "McWeeny runs are driven by a launch sequence per step, not "
+                "by the persistent launch", hipSuccess);
   for (int b = 0; b < count; ++b) {
     const HostInst& h = c->hi[b];
     const double gam = 2.0 * std::max(h.lmax - mu[b], mu[b] - h.lmin);
@@ -1475,6 +1662,7 @@ sp2_status sp2_set_mcweeny(sp2_ctx c, int32_t count, const double* mu,
   c->h_sched_p.assign(alpha.size(), 1);
   c->stretch = std::any_of(alpha.begin(), alpha.end(),
                            [](double x) { return x != 1.0; });
+  release_graph(c);
   for (int b = 0; b < count; ++b) {
     const HostInst& h = c->hi[b];
     Instance& in = c->h_inst[b];
@@ -1572,6 +1760,7 @@ sp2_status sp2_set_homo_lumo(sp2_ctx c, int32_t count, const double* homo_out,
   c->h_sched_p = pol;
   c->stretch = std::any_of(alpha.begin(), alpha.end(),
                            [](double x) { return x != 1.0; });
+  release_graph(c);
   double* d_alpha = static_cast<double*>(c->d_sched);
   int8_t* d_pol = reinterpret_cast<int8_t*>(static_cast<char*>(c->d_sched) + abytes);
   SP2_HIP(c, hipMemcpyAsync(d_alpha, alpha.data(), abytes,

@@ -291,6 +291,39 @@ struct SquareArgs {
   int* bcnt;      // per tail tile: bands finished (0 between launches)
 };
 
+// Persistent batch: one launch runs every step of every instance. Work
+// items (instance, tile, step) sit in a queue in device memory; a workgroup
+// takes the next index, waits until that item is published, computes the
+// tile, and the workgroup that finishes the last tile of an instance's step
+// runs that instance's scalar step and publishes the tiles of its next step.
+struct PItem {
+  int32_t inst;
+  int32_t slot;   // global tile index
+  int32_t iter;   // step i: X~_{i-1} -> X~_i
+  int32_t seq;    // index + 1 once the item is published (0 before)
+};
+struct PQueue {
+  PItem* items;
+  int32_t cap;          // items available (every step of every instance)
+  int32_t count;        // instances
+  int32_t* ctl;         // [0] next index to take, [1] next index to publish,
+                        // [2] nonzero once a wait exceeded its limit
+  int32_t* cnt;         // per instance: tiles of its current step finished
+  int32_t* ndone;       // instances with an outcome
+  HostMirror* mirror;
+  long long wait_limit; // constant-clock ticks a workgroup waits for an item
+};
+// Configurations (0-based ids) the persistent kernel is compiled for.
+bool persist_supported(int cfg);
+// Workgroups of the persistent kernel that fit on the device at once.
+int persist_grid(int cfg, bool stretch, int num_cus);
+// Clears the queue and publishes step 1 of every instance still running
+// after the affine start's finalize.
+hipError_t launch_persist_seed(const Instance* inst, int count, const PQueue& q,
+                               hipStream_t s);
+hipError_t launch_persist(int cfg, const SquareArgs& a, const PQueue& q,
+                          int grid, hipStream_t s);
+
 // Arguments of one spectral-norm launch: every running instance with a
 // chunk table entry (instance, first row) per kSpecRows rows.
 struct SpecArgs {

@@ -51,7 +51,7 @@ def test_default_options_and_kernel_configs():
     opt = sp2.Options()
     lib.sp2_default_options(ctypes.byref(opt))
     assert (opt.precision, opt.branch, opt.trunc_tau, opt.max_iter, opt.kernel_config,
-            opt.tail_split, opt.kernel_timing, opt.norm, opt.reserved) == \
+            opt.tail_split, opt.kernel_timing, opt.norm, opt.launch) == \
         (0, 0, 0.0, 100, 0, 0, 0, 0, 0)
     assert ctypes.sizeof(sp2.Options) == 40
     cfgs = sp2.kernel_configs()

@@ -54,16 +54,19 @@ def test_batch_matches_oracle_per_instance(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
 def test_batch_equals_single_runs_bitwise(prec):
-    """Without tail splits a batch instance runs exactly the arithmetic of a
-    single run of the same configuration: results and histories are equal
-    bit for bit, and every instance stops on its own step."""
+    """Driven by a launch sequence per step without tail splits, a batch
+    instance runs exactly the arithmetic of a single run of the same
+    configuration: results and histories are equal bit for bit, and every
+    instance stops on its own step. (The persistent driver runs a batch with
+    one configuration; its equality with this driver is in
+    test_gpu_persistent.py.)"""
     import torch
     import paper_1507_02087_amd as sp2
     insts = _mixed_instances()
     Fs = _to_gpu(insts)
     res, _ = sp2.run_batch(Fs, [i.lambda_min for i in insts],
                            [i.lambda_max for i in insts], [i.n_occ for i in insts],
-                           precision=prec, tail_split=1)
+                           precision=prec, tail_split=1, launch="sequence")
     stops = set()
     for inst, F, r in zip(insts, Fs, res):
         one = sp2.run_dense(F, inst.lambda_min, inst.lambda_max, inst.n_occ,

@@ -145,10 +145,10 @@ def test_mixed_norm_argument_errors():
     with pytest.raises(sp2.SP2Error) as e:     # Frobenius run: no mixed history
         ctx.get_mixed_history()
     assert e.value.status == sp2.BAD_STATE
-    for norm, reserved in ((3, 0), (-1, 0), (0, 1)):
+    for norm, launch in ((3, 0), (-1, 0), (0, 3), (1, 2)):
         opt = sp2.Options()
         lib.sp2_default_options(ctypes.byref(opt))
-        opt.norm, opt.reserved = norm, reserved
+        opt.norm, opt.launch = norm, launch
         st = lib.sp2_init_dense(ctx._h, ctypes.c_void_p(F.data_ptr()), 64, 64, -1.0, 1.0, 32,
                                 ctypes.byref(opt))
         assert st == sp2.INVALID_ARG
