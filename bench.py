@@ -31,31 +31,46 @@ PEAK_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 PRODUCTS = {"bf16x3": 3, "fp32": 1, "fp64": 1}
 
 
-KERNEL_SOURCE = os.path.join("paper_1507_02087_amd", "csrc", "square_dense.hip")
-
-
 def measured_traffic(config_name: str):
-    """HBM bytes per square step (main + tail kernel) of configuration
-    `config_name`, from the TRAFFIC line of a committed PMC summary under
-    profiles/ (two rocprofv3 passes, FETCH_SIZE and WRITE_SIZE, each scaled by
-    a plain copy of known size). Returned only while the kernel source still
-    hashes to the value recorded with the counters; otherwise None."""
+    """HBM bytes per step of configuration `config_name`, from the TRAFFIC
+    line of a committed PMC summary under profiles/ (two rocprofv3 passes,
+    FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size).
+    The line names the kernel sources it describes and their SHA-256; the
+    figure is returned only while those files still hash to it, else None."""
     import glob
     import hashlib
-    try:
-        with open(os.path.join(ROOT, KERNEL_SOURCE), "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
-    except OSError:
-        return None, None
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as fh:
             for line in fh:
                 if not line.startswith("TRAFFIC "):
                     continue
                 rec = json.loads(line[len("TRAFFIC "):])
-                if rec.get("config") == config_name and rec.get("source_sha256") == sha:
+                if rec.get("config") != config_name:
+                    continue
+                srcs = rec.get("sources") or ([rec["source"]] if rec.get("source") else [])
+                h = hashlib.sha256()
+                try:
+                    for src in srcs:
+                        with open(os.path.join(ROOT, src), "rb") as sf:
+                            h.update(sf.read())
+                except OSError:
+                    continue
+                if srcs and h.hexdigest() == rec.get("source_sha256"):
                     return rec["bytes_per_step"], os.path.relpath(path, ROOT)
     return None, None
+
+
+def calibration_copies(out):
+    """Two plain device copies of 1 GiB at the end of a profiled command: the
+    counters they read scale FETCH_SIZE and WRITE_SIZE to bytes."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["calibration_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+    del src, dst
 
 
 def log(msg: str) -> None:
@@ -313,6 +328,7 @@ def bench_bsr(args):
     # value read once by the epilogue (4 KiB per FP32 block)
     bytes_min = float(sum(stats["nonzero"]) + 2 * sum(stats["stored"])) * 4096
     achieved_gbps = bytes_min / (sum(kt) * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic("BSR32_FP32_step")
     # CPU baseline: the FP64 CSR oracle on its first squares, on this host
     cpu = None
     if not args.no_cpu:
@@ -353,12 +369,15 @@ def bench_bsr(args):
         "mfma_frac_fp32": round(flops / (sum(kt) * 1e-3) / 1e12 / 157.3, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": 8000.0,
                      "unit": "GB/s", "frac": round(achieved_gbps / 8000.0, 4),
-                     "traffic": None,
+                     "traffic": traffic,
                      "kernel": "block-sparse step (index + symbolic + numeric kernels)",
-                     "per_launch_bytes": round(bytes_min / max(1, len(kt)), 0)},
+                     "per_launch_bytes": round(bytes_min / max(1, len(kt)), 0),
+                     "traffic_source": traffic_src},
     }
     if cpu:
         out["cpu_baseline"] = cpu
+    if args.calibrate_copy:
+        calibration_copies(out)
     return out
 
 
@@ -505,13 +524,7 @@ def main() -> int:
     }
 
     if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
-        del src, dst
+        calibration_copies(out)
 
     if not args.no_fp64 and prec != "fp64":
         log("[bench] FP64 comparison run")

@@ -298,13 +298,17 @@ sp2_status sp2_get_bsr_nnzb(sp2_ctx ctx, int64_t* nnzb);
 /* Copies the returned block-sparse iterate (its nonzero blocks only) to
  * caller device arrays: row_ptr_dev (nb + 1), col_idx_dev (nnzb, sorted per
  * row) and blocks_dev (nnzb blocks of 32 x 32, FP64 when as_fp64 != 0 else
- * FP32), nnzb as reported by sp2_get_bsr_nnzb. */
+ * FP32), nnzb as reported by sp2_get_bsr_nnzb. A block counts as nonzero
+ * when its stored form is: where the step after the returned one was
+ * scheduled with a stretch (SP2-ACC, Alg. 4), that form is a X~ + c I, so
+ * a diagonal block of X~ that is all zero can be among the blocks. */
 sp2_status sp2_get_bsr(sp2_ctx ctx, int32_t* row_ptr_dev, int32_t* col_idx_dev,
                        void* blocks_dev, int32_t as_fp64);
 
 /* Work of the last block-sparse run, per step i + 1 (i = 0 .. len-1):
  * stored[i] = blocks of the pattern of X~_{i+1} (the symbolic product),
- * nonzero[i] = nonzero blocks of X~_i that entered the product, products[i]
+ * nonzero[i] = nonzero blocks of the stored X~_i (a X~_i + c I under a
+ * stretch) that entered the product, products[i]
  * = 32 x 32 block products X_IK X_JK^T computed for the upper blocks.
  * *len receives the number of squares. Any array may be NULL. */
 sp2_status sp2_get_bsr_stats(sp2_ctx ctx, int32_t cap, int32_t* len,

@@ -2,22 +2,24 @@
 // setting of sec. 5 and sec. 6, where truncation E_i keeps the iterates
 // sparse). Storage: block-sparse rows (BSR) with 32 x 32 FP32 blocks, both
 // triangles stored (exactly symmetric), column indices sorted per row, and
-// a per-block flag that is 1 when the block holds a nonzero after
-// truncation.
+// a per-block flag that is 1 when the stored block (the operand of the next
+// square, a X~ + c I under a stretch) holds a nonzero after truncation.
 //
 // One step, X~_{i-1} (pattern P, some blocks flagged zero) -> X~_i:
-//   1. index the nonzero blocks P' of X~_{i-1} per row (one workgroup);
-//   2. symbolic product: the pattern Q = P' P' + P' per block row from an
-//      LDS bitmap over the block columns, an exclusive scan of the row
-//      counts, and a fill of the sorted column indices;
-//   3. numeric: one wave per upper block (I, J) of Q, S_IJ = sum over
+//   1. symbolic product: the pattern Q = P' P' + P' + diag (P': the flagged
+//      blocks) per block row from an LDS bitmap over the block columns, an
+//      exclusive scan of the row counts, and a fill of the sorted column
+//      indices and of the list of upper blocks (I, J >= I) with the
+//      position of each one's transpose;
+//   2. numeric: one wave per upper block (I, J) of Q, S_IJ = sum over
 //      K in P'(I) and P'(J) of X_IK X_JK^T (X_KJ = X_JK^T by symmetry) on
 //      v_mfma_f32_32x32x2_f32, then the same fused epilogue as the dense
-//      square (error, polynomial, truncation, FP64 traces) and the mirrored
-//      store of the transposed block; persistent waves walk the blocks with
-//      a fixed stride, so the partial sums are deterministic.
-// Blocks that truncation empties stay in Q with flag 0 and are dropped by
-// the next step's index, so values are never compacted.
+//      square (error, polynomial, truncation, FP64 traces) and the store of
+//      the block and of its transpose; persistent waves walk the upper
+//      blocks with a fixed stride, so the partial sums are deterministic.
+// Blocks that truncation empties stay in Q with flag 0 and are skipped by
+// the next step, so values are never compacted. The index kernel (nonzero
+// blocks per row, in column order) serves the extraction of the result.
 #include "sp2_device.h"
 
 namespace sp2 {
@@ -56,13 +58,12 @@ __device__ void block_exclusive_scan(const int32_t* cnt, int n, int32_t* out,
   if (t == kScanThreads - 1) out[n] = sh[t];
 }
 
-// (1) Index of the nonzero blocks of M, per row, in column order.
+// Index of the flagged blocks of M, per row, in column order (for the
+// extraction of the result).
 __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
-    BsrMat M, int nb, BsrIndex idx, const DevState* st, BsrCounters* ctr,
-    int iter) {
+    BsrMat M, int nb, BsrIndex idx) {
   __shared__ int32_t cnt[2 * kScanThreads];
   __shared__ int32_t sh[kScanThreads];
-  if (st && st->done) return;
   for (int r = threadIdx.x; r < nb; r += kScanThreads) {
     int c = 0;
     for (int q = M.row_ptr[r]; q < M.row_ptr[r + 1]; ++q) c += M.flag[q] ? 1 : 0;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
   __syncthreads();
   block_exclusive_scan(cnt, nb, idx.ptr, sh);
   __syncthreads();
-  if (iter > 0 && threadIdx.x == 0) ctr->nonzero[iter] = idx.ptr[nb];
+
   for (int r = threadIdx.x; r < nb; r += kScanThreads) {
     int o = idx.ptr[r];
     for (int q = M.row_ptr[r]; q < M.row_ptr[r + 1]; ++q)
@@ -83,108 +84,188 @@ __global__ __launch_bounds__(kScanThreads) void bsr_index_kernel(
   }
 }
 
-// (2a) Row bitmaps of Q = P' P' + P' + diag and their popcounts.
-__global__ __launch_bounds__(256) void bsr_symbolic_count_kernel(
-    BsrIndex idx, int nb, int nbw, uint32_t* bitmap, int32_t* qcnt,
-    const DevState* st) {
+// (2a) Row bitmaps of Q = P' P' + P' + diag (P': the flagged blocks of the
+// iterate), the prefix popcounts of their words, and the counts of all and
+// of upper (J >= I) blocks per row. The workgroup first reads the column K
+// and the extent of row K of every flagged block of row I (one thread
+// each), then each wave ORs the flagged columns of its share of those rows
+// into the LDS bitmap. Also counts the flagged blocks (statistics).
+constexpr int kCountThreads = 256;
+
+__global__ __launch_bounds__(kCountThreads) void bsr_symbolic_count_kernel(
+    BsrMat A, int nb, int nbw, BsrSymbolic sym, BsrCounters* ctr,
+    const DevState* st, int iter) {
   __shared__ uint32_t bm[kMaxBlockCols / 32];
-  __shared__ int32_t red[4];
+  __shared__ int32_t rk[kCountThreads][2];
   if (st->done) return;
   const int I = blockIdx.x;
-  for (int w = threadIdx.x; w < nbw; w += 256) bm[w] = 0;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (int w = t; w < nbw; w += kCountThreads) bm[w] = 0;
+  const int b0 = A.row_ptr[I], b1 = A.row_ptr[I + 1];
   __syncthreads();
-  const int b0 = idx.ptr[I], b1 = idx.ptr[I + 1];
   // the diagonal block is always kept: the identity term of a stretched
   // step (Alg. 4) writes it even where the iterate's block is empty
-  if (threadIdx.x == 0) atomicOr(&bm[I >> 5], 1u << (I & 31));
-  for (int a = b0; a < b1; ++a) {
-    const int K = idx.col[a];
-    if (threadIdx.x == 0) atomicOr(&bm[K >> 5], 1u << (K & 31));
-    for (int q = idx.ptr[K] + threadIdx.x; q < idx.ptr[K + 1]; q += 256) {
-      const int J = idx.col[q];
-      atomicOr(&bm[J >> 5], 1u << (J & 31));
+  if (t == 0) atomicOr(&bm[I >> 5], 1u << (I & 31));
+  int nonzero = 0;
+  for (int a0 = b0; a0 < b1; a0 += kCountThreads) {
+    const int na = min(kCountThreads, b1 - a0);
+    bool nz = false;
+    if (t < na) {
+      rk[t][0] = rk[t][1] = 0;
+      if (A.flag[a0 + t]) {
+        const int K = A.col[a0 + t];
+        atomicOr(&bm[K >> 5], 1u << (K & 31));
+        rk[t][0] = A.row_ptr[K];
+        rk[t][1] = A.row_ptr[K + 1];
+        nz = true;
+      }
     }
+    nonzero += __syncthreads_count(nz);
+    for (int a = wave; a < na; a += kCountThreads / 64)
+      for (int q = rk[a][0] + lane; q < rk[a][1]; q += 64)
+        if (A.flag[q]) {
+          const int J = A.col[q];
+          atomicOr(&bm[J >> 5], 1u << (J & 31));
+        }
+    __syncthreads();
   }
-  __syncthreads();
-  int c = 0;
-  for (int w = threadIdx.x; w < nbw; w += 256) {
-    bitmap[static_cast<size_t>(I) * nbw + w] = bm[w];
-    c += __popc(bm[w]);
+  if (t == 0 && nonzero) atomicAdd(&ctr->nonzero[iter], nonzero);
+  if (wave == 0) {
+    // nbw <= 64: one word per lane
+    const int w = lane;
+    const uint32_t bits = (w < nbw) ? bm[w] : 0u;
+    const int c = __popc(bits);
+    int incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (w < nbw) {
+      sym.bitmap[static_cast<size_t>(I) * nbw + w] = bits;
+      sym.wpre[static_cast<size_t>(I) * nbw + w] = incl - c;
+    }
+    const int wi = I >> 5;
+    const uint32_t um = (w > wi) ? ~0u : (w == wi ? (~0u << (I & 31)) : 0u);
+    int u = __popc(bits & um);
+    for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+    if (lane == 63) sym.qcnt[I] = incl;
+    if (lane == 0) sym.ucnt[I] = u;
   }
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) qcnt[I] = red[0] + red[1] + red[2] + red[3];
 }
 
-// (2b) Row pointers of Q; flags an overflow when Q exceeds the capacity.
+// (2b) Row pointers of Q and of the upper work list; flags an overflow when
+// Q exceeds the capacity.
 __global__ __launch_bounds__(kScanThreads) void bsr_symbolic_scan_kernel(
-    const int32_t* qcnt, int nb, int32_t* row_ptr, int32_t cap,
-    BsrCounters* ctr, const DevState* st, int iter) {
+    BsrSymbolic sym, int nb, int32_t* row_ptr, int32_t cap, BsrCounters* ctr,
+    const DevState* st, int iter) {
   __shared__ int32_t cnt[2 * kScanThreads];
   __shared__ int32_t sh[kScanThreads];
   if (st->done) return;
-  for (int r = threadIdx.x; r < nb; r += kScanThreads) cnt[r] = qcnt[r];
+  for (int r = threadIdx.x; r < nb; r += kScanThreads) cnt[r] = sym.qcnt[r];
   __syncthreads();
   block_exclusive_scan(cnt, nb, row_ptr, sh);
+  __syncthreads();
+  for (int r = threadIdx.x; r < nb; r += kScanThreads) cnt[r] = sym.ucnt[r];
+  __syncthreads();
+  block_exclusive_scan(cnt, nb, sym.uptr, sh);
   __syncthreads();
   if (threadIdx.x == 0) {
     const int total = row_ptr[nb];
     ctr->nnzb = total;
+    ctr->nupper = sym.uptr[nb];
     ctr->stored[iter] = total;
     if (total > cap) ctr->overflow = 1;
   }
 }
 
-// (2c) Sorted column indices (and block rows) of Q from the bitmaps.
+// (2c) Sorted column indices (and block rows) of Q from the bitmaps, and the
+// upper work list: for each block (I, J >= I) its position, the position of
+// (J, I) (row pointer of J plus the rank of I among the columns of row J,
+// from J's bitmap word and its prefix popcount), I and J. One wave per row.
 __global__ __launch_bounds__(64) void bsr_symbolic_fill_kernel(
-    const uint32_t* bitmap, int nb, int nbw, BsrMat Q, const BsrCounters* ctr,
+    BsrSymbolic sym, int nb, int nbw, BsrMat Q, BsrCounters* ctr,
     const DevState* st) {
+  __shared__ int32_t cols[kMaxBlockCols];
   if (st->done || ctr->overflow) return;
   const int I = blockIdx.x;
-  int base = Q.row_ptr[I];
+  const int lane = threadIdx.x;
+  const int row0 = Q.row_ptr[I];
+  const uint32_t* brow_bits = sym.bitmap + static_cast<size_t>(I) * nbw;
+  int base = 0;
   for (int w0 = 0; w0 < nbw; w0 += 64) {
-    const int w = w0 + threadIdx.x;
-    const uint32_t bits = (w < nbw) ? bitmap[static_cast<size_t>(I) * nbw + w] : 0u;
-    int c = __popc(bits);
-    // inclusive prefix over the wave
+    const int w = w0 + lane;
+    const uint32_t bits = (w < nbw) ? brow_bits[w] : 0u;
+    const int c = __popc(bits);
     int incl = c;
     for (int off = 1; off < 64; off <<= 1) {
       const int v = __shfl_up(incl, off, 64);
-      if (threadIdx.x >= off) incl += v;
+      if (lane >= off) incl += v;
     }
     int o = base + incl - c;
     uint32_t b = bits;
     while (b) {
       const int bit = __ffs(b) - 1;
       b &= b - 1;
-      Q.col[o] = 32 * w + bit;
-      Q.brow[o] = I;
+      const int J = 32 * w + bit;
+      cols[o] = J;
+      Q.col[row0 + o] = J;
+      Q.brow[row0 + o] = I;
       ++o;
     }
     base += __shfl(incl, 63, 64);
   }
-}
-
-// Position of column c in the sorted list col[lo..hi), or -1.
-__device__ __forceinline__ int find_col(const int32_t* col, int lo, int hi,
-                                        int c) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    const int v = col[mid];
-    if (v == c) return mid;
-    if (v < c) lo = mid + 1;
-    else hi = mid;
+  __syncthreads();
+  const int count = base;
+  const int wi = I >> 5;
+  const uint32_t low = (1u << (I & 31)) - 1u;
+  // columns before the diagonal block, which is always present
+  const int first = sym.wpre[static_cast<size_t>(I) * nbw + wi] +
+                    __popc(brow_bits[wi] & low);
+  const int u0 = sym.uptr[I];
+  for (int t = first + lane; t < count; t += 64) {
+    const int J = cols[t];
+    const int q = row0 + t;
+    int qT = q;
+    if (J != I) {
+      const uint32_t wj = sym.bitmap[static_cast<size_t>(J) * nbw + wi];
+      if (!((wj >> (I & 31)) & 1u)) {
+        // (J, I) missing: the pattern is not symmetric (F was not)
+        atomicOr(&ctr->overflow, 2);
+        continue;
+      }
+      qT = Q.row_ptr[J] + sym.wpre[static_cast<size_t>(J) * nbw + wi] +
+           __popc(wj & low);
+    }
+    BsrWork wk;
+    wk.q = q;
+    wk.qT = qT;
+    wk.I = I;
+    wk.J = J;
+    sym.work[u0 + t - first] = wk;
   }
-  return -1;
 }
 
-// (3) Numeric product and fused epilogue. Persistent: wave g of G handles
-// blocks g, g + G, ... of Q (upper ones only).
-__global__ __launch_bounds__(256) void bsr_numeric_kernel(
-    BsrMat A, BsrIndex idx, BsrMat B, BsrCounters* ctr,
+// (3) Numeric product and fused epilogue. Wave g of G takes the upper blocks
+// g, g + G, ... of the work list, so its partial sums are deterministic.
+// Per block: the nonzero columns K of rows I and J (one per lane), the
+// common ones found by comparing each of row I's columns with every
+// column of row J (broadcast lane by lane), then the products X_IK X_JK^T
+// with the operands of the next product loaded during the current one's
+// MFMAs, and the old block X_IJ loaded beside the first product.
+__device__ __forceinline__ void load_block_frag(const float* val, int p, int r,
+                                                int h, floatx4 (&f)[4]) {
+  const float* b = val + static_cast<size_t>(p) * BE + r * BS + h * 16;
+  for (int u = 0; u < 4; ++u) f[u] = *gro(reinterpret_cast<const floatx4*>(b + 4 * u));
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
+    BsrMat A, BsrMat B, const BsrWork* __restrict__ work, BsrCounters* ctr,
     const Instance* inst, int iter, int n, double* part) {
   __shared__ double sh[4][3];
+  __shared__ unsigned long long shp[4];
+  __shared__ __attribute__((aligned(16))) float old_lds[4][BE];
   const Instance& in = inst[0];
   const DevState* st = in.st;
   if (st->done) return;
@@ -198,98 +279,152 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     }
     return;
   }
-  // the step squares the stored Y = a X~ + c I (OpMap); X_i = S or 2 Y - S,
-  // the error of X~ from Y and S, and the stored output is the next step's
-  // matrix an X~_i + cn I
-  const bool p1 = st->p[iter] != 0;
-  const StepCoef k{st->ecoef[0], st->ecoef[1], st->ecoef[2], st->ecoef[3],
-                   st->ecoef[4]};
-  const bool stretch = st->stretch != 0;
-  const float ka = p1 ? 1.f : -1.f, kb = p1 ? 0.f : 2.f;
-  const double tau = in.tau;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = lane & 31, h = lane >> 5;
-  const int total = ctr->nnzb;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int total = ctr->nupper;
   const int G = gridDim.x * 4;
   double sv = 0.0, st1 = 0.0, st2 = 0.0;
   unsigned long long nprod = 0;
-  for (int q = blockIdx.x * 4 + wave; q < total; q += G) {
-    const int I = B.brow[q], J = B.col[q];
-    if (J < I) continue;
-    // S_IJ = sum_K X_IK X_JK^T over K in P'(I) and P'(J), in K order.
+  for (int u = blockIdx.x * 4 + wave; u < total; u += G) {
+    // The lane's row and half, made opaque per block so that the compiler
+    // does not hoist the 16 elements' lane masks and addresses out of the
+    // loop (they would not fit in registers).
+    int lr = lane;
+    asm volatile("" : "+v"(lr));
+    const int r = lr & 31, h = lr >> 5;
+    // wave-uniform values (kept in scalar registers)
+    const BsrWork wk = work[u];
+    const int q = uni(wk.q), qT = uni(wk.qT), I = uni(wk.I), J = uni(wk.J);
+    const bool diag = (I == J);
+    const int i0 = uni(A.row_ptr[I]), i1 = uni(A.row_ptr[I + 1]);
+    const int j0 = uni(A.row_ptr[J]), j1 = uni(A.row_ptr[J + 1]);
     floatx16 acc;
     for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-    const int i0 = idx.ptr[I], i1 = idx.ptr[I + 1];
-    const int j0 = idx.ptr[J], j1 = idx.ptr[J + 1];
+    int po = -1;             // position of the old block X_IJ, if row I holds it
     for (int c0 = i0; c0 < i1; c0 += 64) {
-      int posI = -1, posJ = -1;
-      if (c0 + lane < i1) {
-        const int K = idx.col[c0 + lane];
-        const int m = find_col(idx.col, j0, j1, K);
-        if (m >= 0) {
-          posI = idx.pos[c0 + lane];
-          posJ = idx.pos[m];
+      const bool vi = c0 + lane < i1 && A.flag[c0 + lane] != 0;
+      const int K = vi ? A.col[c0 + lane] : -1;
+      const int pI = c0 + lane;
+      const unsigned long long mo = __ballot(K == J);
+      if (mo) {
+        po = __builtin_amdgcn_readlane(pI, __ffsll(static_cast<long long>(mo)) - 1);
+        // the old block goes straight to this wave's LDS area (four loads
+        // of 64 x 16 bytes) while the products run
+        const char* gb = reinterpret_cast<const char*>(A.val + static_cast<size_t>(po) * BE);
+        for (int kq = 0; kq < 4; ++kq)
+          __builtin_amdgcn_global_load_lds(
+              (const __attribute__((address_space(1))) void*)(gb + kq * 1024 + 16 * lane),
+              (__attribute__((address_space(3))) void*)(&old_lds[wave][kq * 256]), 16, 0, 0);
+      }
+      int pJ = -1;
+      for (int d0 = j0; d0 < j1; d0 += 64) {
+        const bool vj = d0 + lane < j1 && A.flag[d0 + lane] != 0;
+        const int KJ = vj ? A.col[d0 + lane] : -2;
+        const int PJ = d0 + lane;
+        const int m = min(64, j1 - d0);
+        for (int t = 0; t < m; ++t) {
+          const int kt = __builtin_amdgcn_readlane(KJ, t);
+          const int pt = __builtin_amdgcn_readlane(PJ, t);
+          if (K == kt) pJ = pt;
         }
       }
-      unsigned long long mask = __ballot(posI >= 0);
+      unsigned long long mask = __ballot(vi && pJ >= 0);
       nprod += __popcll(mask);
-      while (mask) {
-        const int src = __ffsll(static_cast<long long>(mask)) - 1;
-        mask &= mask - 1;
-        const int pa = __shfl(posI, src, 64), pb = __shfl(posJ, src, 64);
-        const float* ab = A.val + static_cast<size_t>(pa) * BE + r * BS + h * 16;
-        const float* bb = A.val + static_cast<size_t>(pb) * BE + r * BS + h * 16;
-        floatx4 af[4], bf[4];
-        for (int u = 0; u < 4; ++u) {
-          af[u] = *gro(reinterpret_cast<const floatx4*>(ab + 4 * u));
-          bf[u] = *gro(reinterpret_cast<const floatx4*>(bb + 4 * u));
+      // products in mask order; the next product's blocks load while the
+      // current one's MFMAs run
+      if (!mask) continue;
+      floatx4 fa[4], fb[4];
+      int src = __ffsll(static_cast<long long>(mask)) - 1;
+      mask &= mask - 1;
+      load_block_frag(A.val, __builtin_amdgcn_readlane(pI, src), r, h, fa);
+      load_block_frag(A.val, __builtin_amdgcn_readlane(pJ, src), r, h, fb);
+      for (;;) {
+        const bool more = mask != 0;
+        floatx4 na[4], nb[4];
+        if (more) {
+          src = __ffsll(static_cast<long long>(mask)) - 1;
+          mask &= mask - 1;
+          load_block_frag(A.val, __builtin_amdgcn_readlane(pI, src), r, h, na);
+          load_block_frag(A.val, __builtin_amdgcn_readlane(pJ, src), r, h, nb);
         }
         for (int s = 0; s < 16; ++s)
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af[s >> 2][s & 3],
-                                                     bf[s >> 2][s & 3], acc,
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s >> 2][s & 3],
+                                                     fb[s >> 2][s & 3], acc,
                                                      0, 0, 0);
+        if (!more) break;
+        for (int v = 0; v < 4; ++v) {
+          fa[v] = na[v];
+          fb[v] = nb[v];
+        }
       }
     }
-    // Epilogue. Old block X_IJ (zero if absent or emptied).
-    const int po = find_col(idx.col, i0, i1, J);
-    const float* old = (po >= 0) ? A.val + static_cast<size_t>(idx.pos[po]) * BE
-                                 : nullptr;
-    const int qT = (I == J) ? q : find_col(B.col, B.row_ptr[J], B.row_ptr[J + 1], I);
-    if (qT < 0) {
-      // (J, I) missing: the pattern is not symmetric (F was not).
-      if (lane == 0) atomicOr(&ctr->overflow, 2);
-      continue;
+    float xo[16];
+    if (po >= 0) {
+      __builtin_amdgcn_s_waitcnt(0);   // this wave's old block is in LDS
+      const float* ol = &old_lds[wave][4 * h * BS + r];
+      for (int j = 0; j < 16; ++j) xo[j] = ol[(8 * (j >> 2) + (j & 3)) * BS];
+    } else {
+      for (int j = 0; j < 16; ++j) xo[j] = 0.f;
     }
+    // the step squares the stored Y = a X~ + c I (OpMap); X_i = S or 2 Y - S,
+    // the error of X~ from Y and S, and the stored output is the next step's
+    // matrix an X~_i + cn I
+    const bool p1 = st->p[iter] != 0;
+    const StepCoef k{st->ecoef[0], st->ecoef[1], st->ecoef[2], st->ecoef[3],
+                     st->ecoef[4]};
+    const bool stretch = st->stretch != 0;
+    const float ka = p1 ? 1.f : -1.f, kb = p1 ? 0.f : 2.f;
+    const double tau = in.tau;
+    // Epilogue (acc[j] is element (m, r) of S_IJ, m = 8 (j/4) + 4 h + j%4).
     float* out = B.val + static_cast<size_t>(q) * BE;
     float* outT = B.val + static_cast<size_t>(qT) * BE;
     bool nz = false;
     double bsq = 0.0;   // squared Frobenius norm of this block of X~ - S
+    float xs[16];
     for (int j = 0; j < 16; ++j) {
       const int m = 8 * (j >> 2) + 4 * h + (j & 3);   // row in the block
       const int c = r;                                // column in the block
-      if (I == J && m > c) continue;
+      xs[j] = 0.f;
+      if (diag && m > c) continue;
       const float s = acc[j];
-      const float xo = old ? *gro(old + m * BS + c) : 0.f;
       // identity terms only inside the matrix proper
-      const bool on = (I == J && m == c && I * BS + m < n);
+      const bool on = (diag && m == c && I * BS + m < n);
       const double d = __builtin_fma(k.es, static_cast<double>(s),
-                                     k.ey * static_cast<double>(xo)) +
+                                     k.ey * static_cast<double>(xo[j])) +
                        (on ? k.ei : 0.0);
-      const double w = (I == J && m == c) ? 1.0 : 2.0;
+      const double w = (diag && m == c) ? 1.0 : 2.0;
       sv += w * d * d;
-      bsq += (I == J) ? w * d * d : d * d;
-      float xn = __builtin_fmaf(kb, xo, ka * s);
+      bsq += diag ? w * d * d : d * d;
+      float xn = __builtin_fmaf(kb, xo[j], ka * s);
       double xd = static_cast<double>(xn);
       if (fabs(xd) < tau) {
         xn = 0.f;
         xd = 0.0;
       }
       st2 += w * xd * xd;
-      if (I == J && m == c) st1 += xd;
-      nz = nz || (xn != 0.f);
+      if (diag && m == c) st1 += xd;
       if (stretch) xn = static_cast<float>(__builtin_fma(k.an, xd, on ? k.cn : 0.0));
-      *grw(out + m * BS + c) = xn;
-      if (!(I == J && m == c)) *grw(outT + c * BS + m) = xn;
+      nz = nz || (xn != 0.f);   // the stored block, the next step's operand
+      xs[j] = xn;
+    }
+    float* ob = out + 4 * h * BS + r;           // element (4 h, r)
+    float* obT = outT + r * BS + 4 * h;         // element (r, 4 h)
+    if (diag) {
+      // upper elements and their mirror images
+      for (int j = 0; j < 16; ++j) {
+        const int m = 8 * (j >> 2) + 4 * h + (j & 3);
+        const int o = 8 * (j >> 2) + (j & 3);
+        if (m <= r) *grw(ob + o * BS) = xs[j];
+        if (m < r) *grw(obT + o) = xs[j];
+      }
+    } else {
+      for (int j = 0; j < 16; ++j) *grw(ob + (8 * (j >> 2) + (j & 3)) * BS) = xs[j];
+      // the transposed block: four consecutive elements of row r per store
+      for (int g = 0; g < 4; ++g) {
+        floatx4 v4;
+        for (int e = 0; e < 4; ++e) v4[e] = xs[4 * g + e];
+        *grw(reinterpret_cast<floatx4*>(obT + 8 * g)) = v4;
+      }
     }
     const int any = __any(nz) ? 1 : 0;
     if (lane == 0) {
@@ -313,10 +448,12 @@ __global__ __launch_bounds__(256) void bsr_numeric_kernel(
     sh[wave][0] = sv;
     sh[wave][1] = st1;
     sh[wave][2] = st2;
+    shp[wave] = nprod;
   }
   __syncthreads();
-  if (lane == 0 && nprod) atomicAdd(&ctr->products[iter], nprod);
   if (threadIdx.x == 0) {
+    const unsigned long long np = shp[0] + shp[1] + shp[2] + shp[3];
+    if (np) atomicAdd(&ctr->products[iter], np);
     part[3 * blockIdx.x + 0] = sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0];
     part[3 * blockIdx.x + 1] = sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1];
     part[3 * blockIdx.x + 2] = sh[0][2] + sh[1][2] + sh[2][2] + sh[3][2];
@@ -355,15 +492,17 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(
     }
     const float xs = static_cast<float>(x);
     const double xd = static_cast<double>(xs);
-    // stored: the matrix of step 1 (a X~_0 + c I with a stretch)
-    X.val[static_cast<size_t>(q) * BE + e] =
+    // stored: the matrix of step 1 (a X~_0 + c I with a stretch); the flag
+    // describes the stored block
+    const float xst =
         (stretch && !trivial)
             ? static_cast<float>(__builtin_fma(m1.a, xd,
                                                (gi == gj && gi < n) ? m1.c : 0.0))
             : xs;
+    X.val[static_cast<size_t>(q) * BE + e] = xst;
     t2 += xd * xd;
     if (gi == gj) t1 += xd;
-    nz = nz || (xs != 0.f);
+    nz = nz || (xst != 0.f);
   }
   t1 = wave_sum(t1);
   t2 = wave_sum(t2);
@@ -437,37 +576,36 @@ hipError_t launch_bsr_reset(BsrCounters* ctr, hipStream_t s) {
 }
 
 hipError_t launch_bsr_index(const BsrMat& M, int nb, const BsrIndex& idx,
-                            const DevState* st, BsrCounters* ctr, int iter,
                             hipStream_t s) {
   hipLaunchKernelGGL(bsr_index_kernel, dim3(1), dim3(kScanThreads), 0, s, M,
-                     nb, idx, st, ctr, iter);
+                     nb, idx);
   return hipGetLastError();
 }
 
-hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
-                               int32_t* qcnt, const BsrMat& Q, int32_t cap,
-                               BsrCounters* ctr, const DevState* st, int iter,
-                               hipStream_t s) {
+hipError_t launch_bsr_symbolic(const BsrMat& A, int nb,
+                               const BsrSymbolic& sym, const BsrMat& Q,
+                               int32_t cap, BsrCounters* ctr,
+                               const DevState* st, int iter, hipStream_t s) {
   const int nbw = (nb + 31) / 32;
-  hipLaunchKernelGGL(bsr_symbolic_count_kernel, dim3(nb), dim3(256), 0, s, idx,
-                     nb, nbw, bitmap, qcnt, st);
+  hipLaunchKernelGGL(bsr_symbolic_count_kernel, dim3(nb), dim3(kCountThreads),
+                     0, s, A, nb, nbw, sym, ctr, st, iter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bsr_symbolic_scan_kernel, dim3(1), dim3(kScanThreads), 0,
-                     s, qcnt, nb, Q.row_ptr, cap, ctr, st, iter);
+                     s, sym, nb, Q.row_ptr, cap, ctr, st, iter);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bsr_symbolic_fill_kernel, dim3(nb), dim3(64), 0, s,
-                     bitmap, nb, nbw, Q, ctr, st);
+  hipLaunchKernelGGL(bsr_symbolic_fill_kernel, dim3(nb), dim3(64), 0, s, sym,
+                     nb, nbw, Q, ctr, st);
   return hipGetLastError();
 }
 
-hipError_t launch_bsr_numeric(const BsrMat& A, const BsrIndex& idx,
-                              const BsrMat& B, BsrCounters* ctr,
+hipError_t launch_bsr_numeric(const BsrMat& A, const BsrMat& B,
+                              const BsrWork* work, BsrCounters* ctr,
                               const Instance* inst, int iter, int n,
                               double* part, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(bsr_numeric_kernel, dim3(grid), dim3(256), 0, s, A, idx,
-                     B, ctr, inst, iter, n, part);
+  hipLaunchKernelGGL(bsr_numeric_kernel, dim3(grid), dim3(256), 0, s, A, B,
+                     work, ctr, inst, iter, n, part);
   return hipGetLastError();
 }
 

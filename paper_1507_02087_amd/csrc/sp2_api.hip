@@ -161,8 +161,7 @@ struct sp2_ctx_s {
     const double* F = nullptr;
     sp2::BsrMat m[2] = {};
     sp2::BsrIndex idx = {};
-    uint32_t* bitmap = nullptr;
-    int32_t* qcnt = nullptr;
+    sp2::BsrSymbolic sym = {};
     sp2::BsrCounters* ctr = nullptr;
     sp2::BsrCounters host_ctr = {};   // counters of the last run
     size_t bytes = 0;              // bytes of the allocation below
@@ -854,12 +853,9 @@ sp2_status run_batch(sp2_ctx c) {
     if (c->bsr) {
       const sp2::BsrMat& cur = c->b.m[(i - 1) & 1];
       const sp2::BsrMat& nxt = c->b.m[i & 1];
-      SP2_HIP(c, sp2::launch_bsr_index(cur, c->b.nb, c->b.idx, c->d_st,
-                                       c->b.ctr, i, s));
-      SP2_HIP(c, sp2::launch_bsr_symbolic(c->b.idx, c->b.nb, c->b.bitmap,
-                                          c->b.qcnt, nxt, c->b.cap, c->b.ctr,
-                                          c->d_st, i, s));
-      SP2_HIP(c, sp2::launch_bsr_numeric(cur, c->b.idx, nxt, c->b.ctr,
+      SP2_HIP(c, sp2::launch_bsr_symbolic(cur, c->b.nb, c->b.sym, nxt,
+                                          c->b.cap, c->b.ctr, c->d_st, i, s));
+      SP2_HIP(c, sp2::launch_bsr_numeric(cur, nxt, c->b.sym.work, c->b.ctr,
                                          c->d_inst, i,
                                          static_cast<int>(c->b.n), c->d_part,
                                          c->b.grid, s));
@@ -947,11 +943,10 @@ sp2_status run_batch(sp2_ctx c) {
   return SP2_OK;
 }
 
-// Index of the nonzero blocks of the returned block-sparse iterate.
+// Index of the flagged blocks of the returned block-sparse iterate.
 sp2_status bsr_result_index(sp2_ctx c, int64_t* nnzb) {
   const sp2::BsrMat& m = c->b.m[c->host_state[0].n & 1];
-  SP2_HIP(c, sp2::launch_bsr_index(m, c->b.nb, c->b.idx, nullptr, c->b.ctr, 0,
-                                   c->stream));
+  SP2_HIP(c, sp2::launch_bsr_index(m, c->b.nb, c->b.idx, c->stream));
   int32_t cnt = 0;
   SP2_HIP(c, hipMemcpyAsync(&cnt, c->b.idx.ptr + c->b.nb, sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
@@ -1367,7 +1362,11 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   const size_t o_ic = take(cap * sizeof(int32_t));
   const size_t o_is = take(cap * sizeof(int32_t));
   const size_t o_bm = take(static_cast<size_t>(nb) * nbw * sizeof(uint32_t));
+  const size_t o_wp = take(static_cast<size_t>(nb) * nbw * sizeof(int32_t));
   const size_t o_qc = take(nb * sizeof(int32_t));
+  const size_t o_uc = take(nb * sizeof(int32_t));
+  const size_t o_up = take((nb + 1) * sizeof(int32_t));
+  const size_t o_wk = take(static_cast<size_t>(cap) * sizeof(sp2::BsrWork));
   const size_t o_ct = take(sizeof(sp2::BsrCounters));
   if (off > c->b.bytes) {
     SP2_HIP(c, hipStreamSynchronize(c->stream));
@@ -1388,8 +1387,12 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   c->b.idx.ptr = reinterpret_cast<int32_t*>(base + o_ip);
   c->b.idx.col = reinterpret_cast<int32_t*>(base + o_ic);
   c->b.idx.pos = reinterpret_cast<int32_t*>(base + o_is);
-  c->b.bitmap = reinterpret_cast<uint32_t*>(base + o_bm);
-  c->b.qcnt = reinterpret_cast<int32_t*>(base + o_qc);
+  c->b.sym.bitmap = reinterpret_cast<uint32_t*>(base + o_bm);
+  c->b.sym.wpre = reinterpret_cast<int32_t*>(base + o_wp);
+  c->b.sym.qcnt = reinterpret_cast<int32_t*>(base + o_qc);
+  c->b.sym.ucnt = reinterpret_cast<int32_t*>(base + o_uc);
+  c->b.sym.uptr = reinterpret_cast<int32_t*>(base + o_up);
+  c->b.sym.work = reinterpret_cast<sp2::BsrWork*>(base + o_wk);
   c->b.ctr = reinterpret_cast<sp2::BsrCounters*>(base + o_ct);
   c->b.n = n;
   c->b.nb = nb;

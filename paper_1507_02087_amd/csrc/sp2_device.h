@@ -388,10 +388,29 @@ struct BsrIndex {
   int32_t* pos;
 };
 
+// One upper block (J >= I) of the pattern being built: its storage position,
+// the position of its transpose (J, I), and its block row and column.
+struct BsrWork {
+  int32_t q, qT, I, J;
+};
+
+// Symbolic product buffers: per block row, the bitmap of the pattern's
+// columns, the exclusive prefix of the bitmap words' popcounts, the counts
+// of all and of upper blocks, and the row pointers of the upper work list.
+struct BsrSymbolic {
+  uint32_t* bitmap;   // nb x nbw
+  int32_t* wpre;      // nb x nbw
+  int32_t* qcnt;      // nb
+  int32_t* ucnt;      // nb
+  int32_t* uptr;      // nb + 1
+  BsrWork* work;      // capacity
+};
+
 struct BsrCounters {
   int32_t nnzb;       // stored blocks of the pattern being built
   int32_t overflow;   // 1: capacity exceeded; 2: pattern not symmetric
-  int32_t pad[2];
+  int32_t nupper;     // upper blocks of that pattern (work list length)
+  int32_t pad;
   // per step i: blocks of the pattern of X~_i, nonzero blocks of X~_{i-1},
   // and block products X_IK X_JK^T computed
   int32_t stored[kMaxIter + 2];
@@ -400,16 +419,17 @@ struct BsrCounters {
 };
 
 hipError_t launch_bsr_reset(BsrCounters* ctr, hipStream_t s);
-// iter > 0 records the count of nonzero blocks in ctr->nonzero[iter].
+// Index of the flagged blocks of M per row (extraction of the result).
 hipError_t launch_bsr_index(const BsrMat& M, int nb, const BsrIndex& idx,
-                            const DevState* st, BsrCounters* ctr, int iter,
                             hipStream_t s);
-hipError_t launch_bsr_symbolic(const BsrIndex& idx, int nb, uint32_t* bitmap,
-                               int32_t* qcnt, const BsrMat& Q, int32_t cap,
-                               BsrCounters* ctr, const DevState* st, int iter,
-                               hipStream_t s);
-hipError_t launch_bsr_numeric(const BsrMat& A, const BsrIndex& idx,
-                              const BsrMat& B, BsrCounters* ctr,
+// Symbolic product of step iter from the flagged blocks of A: the pattern Q
+// and the upper work list; counts A's flagged blocks in ctr->nonzero[iter].
+hipError_t launch_bsr_symbolic(const BsrMat& A, int nb,
+                               const BsrSymbolic& sym, const BsrMat& Q,
+                               int32_t cap, BsrCounters* ctr,
+                               const DevState* st, int iter, hipStream_t s);
+hipError_t launch_bsr_numeric(const BsrMat& A, const BsrMat& B,
+                              const BsrWork* work, BsrCounters* ctr,
                               const Instance* inst, int iter, int n,
                               double* part, int grid, hipStream_t s);
 hipError_t launch_bsr_f0(const double* F, const BsrMat& X, int nnzb,

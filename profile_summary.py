@@ -16,8 +16,14 @@ second a WRITE_SIZE pass of the same command, which ends with plain device
 copies of --copy-bytes bytes. Each counter is scaled by the copy's known bytes
 over what the counter reads for the copy; the scaled fetch and write bytes of
 the matching kernels (main and tail kernel of one step) are summed per step
-and printed as one TRAFFIC line with the SHA-256 of the kernel source, so a
-reader can tell whether the figure still describes the current kernel.
+and printed as one TRAFFIC line with the SHA-256 of the kernel sources
+(--source, repeatable; hashed in the given order), so a reader can tell
+whether the figure still describes the current kernels. By default a step's
+bytes are the per-kernel means over the long dispatches; with --per-step N
+they are each kernel's total over all its dispatches divided by N (for a step
+made of several kernels that also run, returning at once, after the stop).
+
+--match takes alternatives separated by '|' (plain substrings).
 """
 from __future__ import annotations
 
@@ -34,8 +40,9 @@ def main() -> int:
     ap.add_argument("--match", default="")
     ap.add_argument("--write-db", default=None)
     ap.add_argument("--copy-bytes", type=float, default=float(1 << 30))
-    ap.add_argument("--source", default=None)
+    ap.add_argument("--source", action="append", default=None)
     ap.add_argument("--config", default=None)
+    ap.add_argument("--per-step", type=int, default=0)
     args = ap.parse_args()
     if args.write_db:
         return traffic(args)
@@ -44,7 +51,7 @@ def main() -> int:
     rows = cur.execute("select id, name, duration from kernels").fetchall()
     by = {}
     for kid, name, dur in rows:
-        if args.match and args.match not in name:
+        if not _matches(name, args.match):
             continue
         by.setdefault(name, []).append((kid, dur / 1e3))
     print(f"# rocprofv3 summary of {args.db}")
@@ -70,7 +77,7 @@ def main() -> int:
         print("\nkernel | counter | long dispatches | mean value per dispatch")
         vals = {}
         for kname, _did, cname, v, dur in pmc:
-            if args.match and args.match not in kname and "copyBuffer" not in kname:
+            if not _matches(kname, args.match) and "copyBuffer" not in kname:
                 continue
             if dur is not None and dur / 1e3 <= args.min_us and "copyBuffer" not in kname:
                 continue
@@ -81,10 +88,15 @@ def main() -> int:
     return 0
 
 
-def _counter_means(db, counter, match, min_us, copy_bytes):
-    """Mean KiB per long dispatch of each matching kernel, and the counter's
-    KiB for the calibration copies (dispatches of the copy kernel reading
-    at least a quarter of copy_bytes)."""
+def _matches(name, match):
+    return not match or any(m in name for m in match.split("|"))
+
+
+def _counter_means(db, counter, match, min_us, copy_bytes, per_step=0):
+    """Mean KiB per long dispatch of each matching kernel (with per_step: the
+    total over all dispatches / per_step), and the counter's KiB for the
+    calibration copies (dispatches of the copy kernel reading at least a
+    quarter of copy_bytes)."""
     cur = sqlite3.connect(db).cursor()
     rows = cur.execute("select kernel_name, value, duration from counters_collection "
                        "where counter_name = ?", (counter,)).fetchall()
@@ -94,11 +106,13 @@ def _counter_means(db, counter, match, min_us, copy_bytes):
             if v * 1024.0 >= 0.25 * copy_bytes:
                 copies.append(v)
             continue
-        if match and match not in kname:
+        if not _matches(kname, match):
             continue
-        if dur is not None and dur / 1e3 <= min_us:
+        if not per_step and dur is not None and dur / 1e3 <= min_us:
             continue
         per.setdefault(kname, []).append(v)
+    if per_step:
+        return {k: sum(v) / per_step for k, v in per.items()}, per, copies
     return {k: statistics.mean(v) for k, v in per.items()}, per, copies
 
 
@@ -106,9 +120,9 @@ def traffic(args) -> int:
     import hashlib
     import json
     fetch, fper, fcopy = _counter_means(args.db, "FETCH_SIZE", args.match,
-                                        args.min_us, args.copy_bytes)
+                                        args.min_us, args.copy_bytes, args.per_step)
     write, wper, wcopy = _counter_means(args.write_db, "WRITE_SIZE", args.match,
-                                        args.min_us, args.copy_bytes)
+                                        args.min_us, args.copy_bytes, args.per_step)
     if not fcopy or not wcopy:
         print("no calibration copy found in the databases", file=sys.stderr)
         return 1
@@ -134,10 +148,15 @@ def traffic(args) -> int:
     rec = {"config": args.config, "kernels": names, "read_bytes": round(tot_r),
            "write_bytes": round(tot_w), "bytes_per_step": round(tot_r + tot_w),
            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)}
+    if args.per_step:
+        rec["per_step"] = args.per_step
     if args.source:
-        with open(args.source, "rb") as fh:
-            rec["source"] = args.source
-            rec["source_sha256"] = hashlib.sha256(fh.read()).hexdigest()
+        h = hashlib.sha256()
+        for path in args.source:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+        rec["sources"] = args.source
+        rec["source_sha256"] = h.hexdigest()
     print("TRAFFIC " + json.dumps(rec))
     return 0
 

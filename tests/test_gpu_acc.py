@@ -279,3 +279,68 @@ def test_acc_block_sparse_matches_truncated_oracle():
     assert err < 1e-4 and err_exact < 1e-3
     plain = oracle.sp2(inst.F.toarray(), inst.lambda_min, inst.lambda_max, inst.n_occ, tau=tau)
     assert n_sq < plain.n_squares
+
+
+def test_acc_block_sparse_empty_diagonal_block():
+    """A stretched step of Alg. 4 squares a X~ + (1 - a) I: where a whole
+    diagonal block of X~ is zero, the stored operand there is still
+    (1 - a) I and must take part in the products. Block-diagonal F
+    (N = 256, eight 32 x 32 blocks) whose last block is lambda_max I, so X~_0
+    and X~_1 are zero there and step 2 (p = 1, a = 1.69) is stretched. GPU
+    (BSR FP32, tau = 1e-5) against the FP64 oracle with the same truncation:
+    D, the polynomials, and the error history while it is well above the
+    FP32 level."""
+    import scipy.sparse as sps
+    import torch
+    import paper_1507_02087_amd as sp2
+    rng = np.random.default_rng(91)
+    n, bs, tau = 256, 32, 1e-5
+    F = np.zeros((n, n))
+    for b in range(8):
+        sl = slice(b * bs, (b + 1) * bs)
+        if b == 7:
+            F[sl, sl] = np.eye(bs)
+        else:
+            ev = np.concatenate([rng.uniform(-1.0, -0.1, 16), rng.uniform(0.1, 1.0, 16)])
+            Q, _ = np.linalg.qr(rng.standard_normal((bs, bs)))
+            F[sl, sl] = (Q * ev) @ Q.T
+    F = (F + F.T) / 2
+    lam = np.linalg.eigvalsh(F)
+    n_occ = 7 * 16
+    b = (float(lam[n_occ - 1]),) * 2 + (float(lam[n_occ]),) * 2
+    sched = oracle.acc_schedule(-1.0, 1.0, *b)
+    # the case is covered: step 2 is a stretched p = 1 step
+    assert sched.p[2] == 1 and sched.alpha[2] > 1.1
+    ref = oracle.sp2_acc(F, -1.0, 1.0, sched, tau=tau)
+    assert ref.status == Status.OK
+    rp, ci, bl = to_bsr_blocks(sps.csr_matrix(F), 32)
+    assert ci.size == 8
+    ctx = sp2.BsrContext(0)
+    try:
+        ctx.init_bsr(n, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(bl)).cuda(), -1.0, 1.0, n_occ,
+                     trunc_tau=tau)
+        ctx.set_homo_lumo(*b)
+        print_case("bsr acc, zero diagonal block under a stretch")
+        st = ctx.run()
+        D = ctx.get_density(as_fp64=True).cpu().numpy()
+        n_it, _, _ = ctx.get_info()
+        h = ctx.get_history()
+    finally:
+        ctx.close()
+    assert st == sp2.OK
+    assert h["p"][1:n_it + 1] == sched.p[1:n_it + 1]
+    err = np.linalg.norm(D - ref.X) / math.sqrt(n_occ)
+    worst = 0.0
+    for k, (a, r) in enumerate(zip(h["v"], ref.v)):
+        if r > 1e-2:
+            worst = max(worst, abs(a - r) / r)
+            assert abs(a - r) <= 1e-4 * r, (k, a, r)
+    # the stop comes when the error stagnates at the working precision: the
+    # oracle with FP32 storage and products stops where the GPU does (the
+    # FP64 one two steps later, at its own rounding level)
+    ref32 = oracle.sp2_acc(F, -1.0, 1.0, sched, tau=tau, working="fp32")
+    print(f"  n_gpu={n_it} n_oracle={ref.n} (fp32 working: {ref32.n}) err={err:.2e} "
+          f"worst history dev {worst:.2e}", flush=True)
+    assert err < 1e-5
+    assert abs(n_it - ref32.n) <= 1

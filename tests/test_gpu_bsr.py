@@ -123,3 +123,30 @@ def test_invalid_patterns_rejected():
             ctx.init_bsr(64, rpt, cit, bl[:len(ci)], -1.0, 1.0, 32)
         assert e.value.status == sp2.INVALID_ARG
     ctx.close()
+
+
+def test_long_rows_and_ragged_tail():
+    """Every block present (dense F as BSR, N = 2390: 75 block rows, the last
+    ragged), so each row of the iterate holds 75 blocks and the product
+    kernel walks its column lists in two chunks of at most 64; against the
+    FP64 oracle on the dense form (no truncation)."""
+    import scipy.sparse as sps
+    import paper_1507_02087_amd as sp2
+    from workloads import dense_instance
+    inst = dense_instance(2390, 1100, -1.0, 1.0, 0.1, seed=2390)
+    print_case("bsr n=2390, all 75 x 75 blocks stored")
+    st, D, n_it, n_sq, ms, hist, _ = _run_bsr(sps.csr_matrix(inst.F), 2390,
+                                             inst.lambda_min, inst.lambda_max,
+                                             inst.n_occ, 0.0)
+    assert st == sp2.OK
+    ref = oracle.sp2(inst.F, inst.lambda_min, inst.lambda_max, inst.n_occ)
+    err = np.linalg.norm(D - ref.X) / math.sqrt(inst.n_occ)
+    De = oracle.density_from_eigenvectors(inst.Q, inst.n_occ)
+    err_exact = np.linalg.norm(D - De) / math.sqrt(inst.n_occ)
+    print(f"  n_gpu={n_it} n_oracle={ref.n} err={err:.2e} exact={err_exact:.2e} "
+          f"{ms:.2f} ms", flush=True)
+    assert err_exact < 2e-5
+    assert abs(n_it - ref.n) <= 2
+    for k, (a, r) in enumerate(zip(hist["v"], ref.v)):
+        if r > 1e-2:
+            assert abs(a - r) <= 1e-4 * r, (k, a, r)
