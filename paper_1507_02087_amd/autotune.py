@@ -2,8 +2,11 @@
 
 For each precision and each dimension in a list, every compiled kernel
 configuration of that precision runs a few SP2 steps on a seeded dense
-input (two-band spectrum) with the library's kernel timing; the fastest
-median square time wins. Consecutive sizes with the same winner are merged
+input (two-band spectrum) with the library's kernel timing (median square
+time, best of three runs). The incumbent, the configuration the library
+picks now (installed table, else its built-in choice), is kept unless a
+challenger is more than 3 % faster, so that run-to-run noise does not
+change the table. Consecutive sizes with the same winner are merged
 into entries (precision, n_max, configuration) and written as JSON, which
 Context.load_kernel_table installs into the library. Configurations are
 recorded by shape (tile, waves, K slice), not by id, so a table survives a
@@ -34,7 +37,24 @@ def _input(n: int):
     return F.cuda(), n // 2
 
 
-def time_config(ctx, F, n_occ, precision, cfg_id, steps=4, reps=2):
+MARGIN = 1.03   # a challenger replaces the incumbent when this much faster
+
+
+def incumbent(ctx, F, n_occ, precision):
+    """The configuration (1-based id) the library picks for this size now."""
+    ctx.init_dense(F, -3.0, 3.0, n_occ, precision=precision, max_iter=1)
+    return ctx.get_config(0)[0]
+
+
+def pick(times, inc):
+    """The fastest configuration, unless the incumbent is within MARGIN."""
+    win = min(times, key=times.get)
+    if inc in times and times[win] * MARGIN >= times[inc]:
+        return inc
+    return win
+
+
+def time_config(ctx, F, n_occ, precision, cfg_id, steps=4, reps=3):
     import numpy as np
     best = None
     for _ in range(reps):
@@ -54,19 +74,22 @@ def autotune(sizes=SIZES, precisions=("fp64", "fp32", "bf16x3"), log=print):
     for n in sizes:
         F, n_occ = _input(n)
         for prec in precisions:
+            inc = incumbent(ctx, F, n_occ, prec)
             row = {}
             for c in cfgs:
                 if c["precision"] != prec:
                     continue
                 row[c["id"]] = time_config(ctx, F, n_occ, prec, c["id"])
-            win = min(row, key=row.get)
-            results.append(dict(n=n, precision=prec, best=win,
+            win = pick(row, inc)
+            results.append(dict(n=n, precision=prec, best=win, incumbent=inc,
                                 ms={str(k): round(v, 5) for k, v in row.items()}))
-            log(f"n={n} {prec}: best id {win} {row[win]:.4f} ms")
+            log(f"n={n} {prec}: incumbent {inc} {row.get(inc, float('nan')):.4f} ms, "
+                f"chosen {win} {row[win]:.4f} ms")
     ctx.close()
     entries = table_entries(results, cfgs)
     return dict(entries=entries, measurements=results,
-                note="median square-kernel time over 4 SP2 steps, best of 2 runs")
+                note="median square-kernel time over 4 SP2 steps, best of 3 runs; "
+                     "the incumbent stays unless a challenger is > 3 % faster")
 
 
 def table_entries(results, cfgs):
