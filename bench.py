@@ -323,12 +323,17 @@ def bench_bsr(args):
     step_ms = float(np.mean(kt))
     prods = stats["products"]
     flops = float(sum(prods)) * 2 * 32 ** 3
-    # algorithmic bytes of the block-sparse steps: every nonzero block of
-    # X~_{i-1} read once, every stored block of X~_i written once and its old
-    # value read once by the epilogue (4 KiB per FP32 block)
-    bytes_min = float(sum(stats["nonzero"]) + 2 * sum(stats["stored"])) * 4096
+    # algorithmic bytes of the block-sparse steps: every flagged block of
+    # X~_{i-1} read once (the old block X_IJ of the epilogue is one of them)
+    # and every stored block of X~_i written once (4 KiB per FP32 block)
+    bytes_min = float(sum(stats["nonzero"]) + sum(stats["stored"])) * 4096
     achieved_gbps = bytes_min / (sum(kt) * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic("BSR32_FP32_step")
+    # the roofline is the larger of the two floors: MFMA time of the block
+    # products at the FP32 peak, HBM time of the minimum bytes
+    t_mfma = flops / 157.3e12
+    t_hbm = bytes_min / 8.0e12
+    mfma_tf = flops / (sum(kt) * 1e-3) / 1e12
     # CPU baseline: the FP64 CSR oracle on its first squares, on this host
     cpu = None
     if not args.no_cpu:
@@ -367,11 +372,19 @@ def bench_bsr(args):
         "stored_blocks_last": stats["stored"][-1] if stats["stored"] else 0,
         "mfma_tflops": round(flops / (sum(kt) * 1e-3) / 1e12, 2),
         "mfma_frac_fp32": round(flops / (sum(kt) * 1e-3) / 1e12 / 157.3, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": 8000.0,
-                     "unit": "GB/s", "frac": round(achieved_gbps / 8000.0, 4),
+        "roofline": ({"bound": "mfma", "achieved": round(mfma_tf, 2), "peak": 157.3,
+                      "unit": "TFLOP/s", "frac": round(mfma_tf / 157.3, 4)}
+                     if t_mfma >= t_hbm else
+                     {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": 8000.0,
+                      "unit": "GB/s", "frac": round(achieved_gbps / 8000.0, 4)}) | {
                      "traffic": traffic,
-                     "kernel": "block-sparse step (index + symbolic + numeric kernels)",
+                     "kernel": "block-sparse step (symbolic count, scan, fill + numeric kernels)",
+                     "per_launch_flops": round(flops / max(1, len(kt)), 0),
                      "per_launch_bytes": round(bytes_min / max(1, len(kt)), 0),
+                     "hbm_min_bytes_gbps": round(achieved_gbps, 1),
+                     "hbm_frac": round(achieved_gbps / 8000.0, 4),
+                     "floors_us": {"mfma": round(t_mfma / max(1, len(kt)) * 1e6, 2),
+                                   "hbm": round(t_hbm / max(1, len(kt)) * 1e6, 2)},
                      "traffic_source": traffic_src},
     }
     if cpu:

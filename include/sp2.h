@@ -94,7 +94,9 @@ typedef enum {
                               the top Ritz value changes by < 1e-12
                               relative) */
   SP2_NORM_SPECTRAL = 2    /* e_k = ||X~_k - X~_k^2||_2, the error of Alg. 2
-                              as printed: dense and batched runs only. Found
+                              as printed (dense, batched and block-sparse
+                              runs; block-sparse products walk the flagged
+                              blocks of each block row). Found
                               by Lanczos on E = X~_k - X~_k^2 applied as
                               X~_k q - X~_k (X~_k q) to the stored iterate in
                               FP64 arithmetic (E is never formed): three-term
@@ -281,7 +283,9 @@ sp2_status sp2_get_norm_times(sp2_ctx ctx, int32_t cap, int32_t* len,
  * owned by the caller; blocks_dev must stay valid until sp2_run returns
  * (row_ptr/col_idx are copied during this call). opt->precision must be
  * SP2_FP32 (NULL opt: SP2_FP32 defaults); trunc_tau is the element
- * threshold. The library keeps room for up to min(nb^2, 16 nnzb + 64 nb)
+ * threshold; every norm applies (the spectral norm's Lanczos products read
+ * the block-sparse iterate). The library keeps room for up to
+ * min(nb^2, 16 nnzb + 64 nb)
  * blocks per iterate; sp2_run reports SP2_OUT_OF_MEMORY when the fill
  * exceeds it. Errors: SP2_INVALID_ARG (the message names the failed check),
  * SP2_OUT_OF_MEMORY, SP2_HIP_ERROR. After this call sp2_run, sp2_get_info,

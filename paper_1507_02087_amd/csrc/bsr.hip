@@ -96,7 +96,8 @@ __global__ __launch_bounds__(kCountThreads) void bsr_symbolic_count_kernel(
     BsrMat A, int nb, int nbw, BsrSymbolic sym, BsrCounters* ctr,
     const DevState* st, int iter) {
   __shared__ uint32_t bm[kMaxBlockCols / 32];
-  __shared__ int32_t rk[kCountThreads][2];
+  __shared__ int32_t rk0[kCountThreads], pfx[kCountThreads + 1];
+  __shared__ int32_t wsum[kCountThreads / 64];
   if (st->done) return;
   const int I = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -108,28 +109,51 @@ __global__ __launch_bounds__(kCountThreads) void bsr_symbolic_count_kernel(
   if (t == 0) atomicOr(&bm[I >> 5], 1u << (I & 31));
   int nonzero = 0;
   for (int a0 = b0; a0 < b1; a0 += kCountThreads) {
+    // thread t: flagged block a0 + t of row I, its column K and the extent
+    // of row K; then the (row, entry) pairs of all those rows are walked as
+    // one flat range, one pair per thread, found through the prefix sums of
+    // the row lengths
     const int na = min(kCountThreads, b1 - a0);
+    int len = 0;
     bool nz = false;
-    if (t < na) {
-      rk[t][0] = rk[t][1] = 0;
-      if (A.flag[a0 + t]) {
-        const int K = A.col[a0 + t];
-        atomicOr(&bm[K >> 5], 1u << (K & 31));
-        rk[t][0] = A.row_ptr[K];
-        rk[t][1] = A.row_ptr[K + 1];
-        nz = true;
+    if (t < na && A.flag[a0 + t]) {
+      const int K = A.col[a0 + t];
+      atomicOr(&bm[K >> 5], 1u << (K & 31));
+      const int r0 = A.row_ptr[K];
+      rk0[t] = r0;
+      len = A.row_ptr[K + 1] - r0;
+      nz = true;
+    }
+    int incl = len;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    nonzero += __syncthreads_count(nz);
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    pfx[t + 1] = base + incl;
+    if (t == 0) pfx[0] = 0;
+    __syncthreads();
+    const int total = pfx[na];
+    for (int p = t; p < total; p += kCountThreads) {
+      // largest a with pfx[a] <= p (rows of length 0 are skipped over)
+      int lo = 0, hi = na;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pfx[mid] <= p) lo = mid;
+        else hi = mid;
+      }
+      const int q = rk0[lo] + (p - pfx[lo]);
+      if (A.flag[q]) {
+        const int J = A.col[q];
+        atomicOr(&bm[J >> 5], 1u << (J & 31));
       }
     }
-    nonzero += __syncthreads_count(nz);
-    for (int a = wave; a < na; a += kCountThreads / 64)
-      for (int q = rk[a][0] + lane; q < rk[a][1]; q += 64)
-        if (A.flag[q]) {
-          const int J = A.col[q];
-          atomicOr(&bm[J >> 5], 1u << (J & 31));
-        }
     __syncthreads();
   }
-  if (t == 0 && nonzero) atomicAdd(&ctr->nonzero[iter], nonzero);
+  if (t == 0) sym.nzrow[I] = nonzero;
   if (wave == 0) {
     // nbw <= 64: one word per lane
     const int w = lane;
@@ -169,11 +193,20 @@ __global__ __launch_bounds__(kScanThreads) void bsr_symbolic_scan_kernel(
   __syncthreads();
   block_exclusive_scan(cnt, nb, sym.uptr, sh);
   __syncthreads();
+  // flagged blocks of the iterate (statistics)
+  int nz = 0;
+  for (int r = threadIdx.x; r < nb; r += kScanThreads) nz += sym.nzrow[r];
+  for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = nz;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    int nzt = 0;
+    for (int w = 0; w < kScanThreads / 64; ++w) nzt += sh[w];
     const int total = row_ptr[nb];
     ctr->nnzb = total;
     ctr->nupper = sym.uptr[nb];
     ctr->stored[iter] = total;
+    ctr->nonzero[iter] = nzt;
     if (total > cap) ctr->overflow = 1;
   }
 }
@@ -245,13 +278,21 @@ __global__ __launch_bounds__(64) void bsr_symbolic_fill_kernel(
   }
 }
 
-// (3) Numeric product and fused epilogue. Wave g of G takes the upper blocks
-// g, g + G, ... of the work list, so its partial sums are deterministic.
-// Per block: the nonzero columns K of rows I and J (one per lane), the
+// (3) Numeric product and fused epilogue, one upper output block (I, J) of
+// the work list per wave at a time. Workgroup b runs on XCD b % 8 (the grid
+// is a multiple of 8); XCD x takes the x-th contiguous eighth of the work
+// list (ordered by block row), so the blocks that neighbouring rows share
+// stay in its L2, and each of its workgroups a contiguous share of that
+// (about one block row). The workgroup's waves take the blocks of their
+// share in turn from an LDS counter, so a wave that drew a block with many
+// products (near the diagonal) does not hold up the others; each block's
+// partial sums go to a slot of its own and are added in block order, so
+// the sums do not depend on which wave took which block.
+// Per block: the flagged columns K of rows I and J (one per lane), the
 // common ones found by comparing each of row I's columns with every
 // column of row J (broadcast lane by lane), then the products X_IK X_JK^T
 // with the operands of the next product loaded during the current one's
-// MFMAs, and the old block X_IJ loaded beside the first product.
+// MFMAs, and the old block X_IJ loaded straight into LDS beside them.
 __device__ __forceinline__ void load_block_frag(const float* val, int p, int r,
                                                 int h, floatx4 (&f)[4]) {
   const float* b = val + static_cast<size_t>(p) * BE + r * BS + h * 16;
@@ -260,12 +301,15 @@ __device__ __forceinline__ void load_block_frag(const float* val, int p, int r,
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+constexpr int kSlots = 64;   // blocks per batch of a workgroup's share
+
 __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
-    BsrMat A, BsrMat B, const BsrWork* __restrict__ work, BsrCounters* ctr,
-    const Instance* inst, int iter, int n, double* part) {
-  __shared__ double sh[4][3];
+    BsrMat A, BsrMat B, const BsrWork* __restrict__ work, uint32_t* prod_wg,
+    BsrCounters* ctr, const Instance* inst, int iter, int n, double* part) {
   __shared__ unsigned long long shp[4];
   __shared__ __attribute__((aligned(16))) float old_lds[4][BE];
+  __shared__ double slot[kSlots][3];
+  __shared__ int next_item;
   const Instance& in = inst[0];
   const DevState* st = in.st;
   if (st->done) return;
@@ -276,16 +320,39 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
       part[3 * blockIdx.x + 0] = NAN;
       part[3 * blockIdx.x + 1] = NAN;
       part[3 * blockIdx.x + 2] = NAN;
+      prod_wg[static_cast<size_t>(iter) * gridDim.x + blockIdx.x] = 0;
     }
     return;
   }
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int total = ctr->nupper;
-  const int G = gridDim.x * 4;
-  double sv = 0.0, st1 = 0.0, st2 = 0.0;
+  const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+  const int x = blockIdx.x % nx;
+  const int gx = gridDim.x / nx, lb = blockIdx.x / nx;
+  const int u_lo = static_cast<int>(static_cast<int64_t>(total) * x / nx);
+  const int u_hi = static_cast<int>(static_cast<int64_t>(total) * (x + 1) / nx);
+  const int w_lo = u_lo + static_cast<int>(static_cast<int64_t>(u_hi - u_lo) * lb / gx);
+  const int w_hi = u_lo + static_cast<int>(static_cast<int64_t>(u_hi - u_lo) * (lb + 1) / gx);
+  double tsum[3] = {0.0, 0.0, 0.0};   // thread 0: the workgroup's sums
+  // the largest float below tau: for a float x, |x| < tau <=> |x| <= tf
+  const double tau_ = in.tau;
+  float tf = static_cast<float>(tau_);
+  if (tf > 0.f && static_cast<double>(tf) >= tau_) tf = __int_as_float(__float_as_int(tf) - 1);
   unsigned long long nprod = 0;
-  for (int u = blockIdx.x * 4 + wave; u < total; u += G) {
+  auto first_cols = [&](int lo, int hi, int none) {
+    return (lo + lane < hi && A.flag[lo + lane] != 0) ? A.col[lo + lane] : none;
+  };
+  for (int bs = w_lo; bs < w_hi; bs += kSlots) {
+    const int be = min(bs + kSlots, w_hi);
+    if (threadIdx.x == 0) next_item = bs;
+    __syncthreads();
+    for (;;) {
+    int u = 0;
+    if (lane == 0) u = atomicAdd(&next_item, 1);
+    u = uni(__shfl(u, 0, 64));
+    if (u >= be) break;
+    double sv = 0.0, st1 = 0.0, st2 = 0.0;
     // The lane's row and half, made opaque per block so that the compiler
     // does not hoist the 16 elements' lane masks and addresses out of the
     // loop (they would not fit in registers).
@@ -302,8 +369,8 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
     for (int j = 0; j < 16; ++j) acc[j] = 0.f;
     int po = -1;             // position of the old block X_IJ, if row I holds it
     for (int c0 = i0; c0 < i1; c0 += 64) {
-      const bool vi = c0 + lane < i1 && A.flag[c0 + lane] != 0;
-      const int K = vi ? A.col[c0 + lane] : -1;
+      const int K = first_cols(c0, i1, -1);
+      const bool vi = K >= 0;
       const int pI = c0 + lane;
       const unsigned long long mo = __ballot(K == J);
       if (mo) {
@@ -318,8 +385,7 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
       }
       int pJ = -1;
       for (int d0 = j0; d0 < j1; d0 += 64) {
-        const bool vj = d0 + lane < j1 && A.flag[d0 + lane] != 0;
-        const int KJ = vj ? A.col[d0 + lane] : -2;
+        const int KJ = first_cols(d0, j1, -2);
         const int PJ = d0 + lane;
         const int m = min(64, j1 - d0);
         for (int t = 0; t < m; ++t) {
@@ -381,11 +447,33 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
     bool nz = false;
     double bsq = 0.0;   // squared Frobenius norm of this block of X~ - S
     float xs[16];
+    if (!diag) {
+      // off the diagonal: every element counts twice (the block and its
+      // transpose), no identity terms; |x| < tau tested as |x| <= tf
+      double e2 = 0.0, x2 = 0.0;
+      for (int j = 0; j < 16; ++j) {
+        const float s = acc[j];
+        const double d = __builtin_fma(k.es, static_cast<double>(s),
+                                       k.ey * static_cast<double>(xo[j]));
+        e2 = __builtin_fma(d, d, e2);
+        float xn = __builtin_fmaf(kb, xo[j], ka * s);
+        if (!(__builtin_fabsf(xn) > tf)) xn = 0.f;
+        const double xd = static_cast<double>(xn);
+        x2 = __builtin_fma(xd, xd, x2);
+        if (stretch) xn = static_cast<float>(k.an * xd);
+        nz = nz || (xn != 0.f);   // the stored block, the next step's operand
+        xs[j] = xn;
+      }
+      sv += 2.0 * e2;
+      st2 += 2.0 * x2;
+      bsq = e2;
+    }
+    if (diag)
     for (int j = 0; j < 16; ++j) {
       const int m = 8 * (j >> 2) + 4 * h + (j & 3);   // row in the block
       const int c = r;                                // column in the block
       xs[j] = 0.f;
-      if (diag && m > c) continue;
+      if (m > c) continue;
       const float s = acc[j];
       // identity terms only inside the matrix proper
       const bool on = (diag && m == c && I * BS + m < n);
@@ -440,23 +528,30 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
         *grw(in.blk + qT) = bn;
       }
     }
+    // this block's partial sums in its slot
+    sv = wave_sum(sv);
+    st1 = wave_sum(st1);
+    st2 = wave_sum(st2);
+    if (lane == 0) {
+      slot[u - bs][0] = sv;
+      slot[u - bs][1] = st1;
+      slot[u - bs][2] = st2;
+    }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int t = 0; t < be - bs; ++t)
+        for (int v = 0; v < 3; ++v) tsum[v] += slot[t][v];
+    __syncthreads();   // the slots and the counter are reused
   }
-  sv = wave_sum(sv);
-  st1 = wave_sum(st1);
-  st2 = wave_sum(st2);
-  if (lane == 0) {
-    sh[wave][0] = sv;
-    sh[wave][1] = st1;
-    sh[wave][2] = st2;
-    shp[wave] = nprod;
-  }
+  if (lane == 0) shp[wave] = nprod;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned long long np = shp[0] + shp[1] + shp[2] + shp[3];
-    if (np) atomicAdd(&ctr->products[iter], np);
-    part[3 * blockIdx.x + 0] = sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0];
-    part[3 * blockIdx.x + 1] = sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1];
-    part[3 * blockIdx.x + 2] = sh[0][2] + sh[1][2] + sh[2][2] + sh[3][2];
+    prod_wg[static_cast<size_t>(iter) * gridDim.x + blockIdx.x] =
+        static_cast<uint32_t>(shp[0] + shp[1] + shp[2] + shp[3]);
+    part[3 * blockIdx.x + 0] = tsum[0];
+    part[3 * blockIdx.x + 1] = tsum[1];
+    part[3 * blockIdx.x + 2] = tsum[2];
   }
 }
 
@@ -601,11 +696,11 @@ hipError_t launch_bsr_symbolic(const BsrMat& A, int nb,
 }
 
 hipError_t launch_bsr_numeric(const BsrMat& A, const BsrMat& B,
-                              const BsrWork* work, BsrCounters* ctr,
+                              const BsrSymbolic& sym, BsrCounters* ctr,
                               const Instance* inst, int iter, int n,
                               double* part, int grid, hipStream_t s) {
   hipLaunchKernelGGL(bsr_numeric_kernel, dim3(grid), dim3(256), 0, s, A, B,
-                     work, ctr, inst, iter, n, part);
+                     sym.work, sym.prod_wg, ctr, inst, iter, n, part);
   return hipGetLastError();
 }
 

@@ -773,7 +773,7 @@ sp2_status run_batch(sp2_ctx c) {
       const sp2::BsrMat& nxt = c->b.m[i & 1];
       SP2_HIP(c, sp2::launch_bsr_symbolic(cur, c->b.nb, c->b.sym, nxt,
                                           c->b.cap, c->b.ctr, c->d_st, i, s));
-      SP2_HIP(c, sp2::launch_bsr_numeric(cur, nxt, c->b.sym.work, c->b.ctr,
+      SP2_HIP(c, sp2::launch_bsr_numeric(cur, nxt, c->b.sym, c->b.ctr,
                                          c->d_inst, i,
                                          static_cast<int>(c->b.n), c->d_part,
                                          c->b.grid, s));
@@ -837,6 +837,18 @@ sp2_status run_batch(sp2_ctx c) {
   if (c->bsr) {
     sp2::BsrCounters& ctr = c->b.host_ctr;
     SP2_HIP(c, hipMemcpy(&ctr, c->b.ctr, sizeof(ctr), hipMemcpyDeviceToHost));
+    // block products per step: the numeric workgroups' counts, summed here
+    const int nst = std::min(steps, c->opt.max_iter);
+    if (nst > 0) {
+      std::vector<uint32_t> pw(static_cast<size_t>(nst + 1) * c->b.grid);
+      SP2_HIP(c, hipMemcpy(pw.data(), c->b.sym.prod_wg, pw.size() * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost));
+      for (int i = 1; i <= nst; ++i) {
+        unsigned long long t = 0;
+        for (int b = 0; b < c->b.grid; ++b) t += pw[static_cast<size_t>(i) * c->b.grid + b];
+        ctr.products[i] = t;
+      }
+    }
     if (ctr.overflow & 1)
       return fail(c, SP2_OUT_OF_MEMORY,
                   "block-sparse iterate exceeded the block capacity", hipSuccess);
@@ -1200,10 +1212,6 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   if (opt.precision != SP2_FP32)
     return fail(c, SP2_INVALID_ARG, "block-sparse runs use SP2_FP32",
                 hipSuccess);
-  if (opt.norm == SP2_NORM_SPECTRAL)
-    return fail(c, SP2_INVALID_ARG,
-                "block-sparse runs use the Frobenius or the mixed norm",
-                hipSuccess);
   if (block != sp2::kBsrBlock)
     return fail(c, SP2_INVALID_ARG, "block must be 32", hipSuccess);
   if (n <= 0 || n > static_cast<int64_t>(sp2::kMaxBlockCols) * sp2::kBsrBlock)
@@ -1284,6 +1292,8 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   const size_t o_qc = take(nb * sizeof(int32_t));
   const size_t o_uc = take(nb * sizeof(int32_t));
   const size_t o_up = take((nb + 1) * sizeof(int32_t));
+  const size_t o_nz = take(nb * sizeof(int32_t));
+  const size_t o_pw = take(static_cast<size_t>(sp2::kMaxIter + 2) * grid * sizeof(uint32_t));
   const size_t o_wk = take(static_cast<size_t>(cap) * sizeof(sp2::BsrWork));
   const size_t o_ct = take(sizeof(sp2::BsrCounters));
   if (off > c->b.bytes) {
@@ -1310,6 +1320,8 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   c->b.sym.qcnt = reinterpret_cast<int32_t*>(base + o_qc);
   c->b.sym.ucnt = reinterpret_cast<int32_t*>(base + o_uc);
   c->b.sym.uptr = reinterpret_cast<int32_t*>(base + o_up);
+  c->b.sym.nzrow = reinterpret_cast<int32_t*>(base + o_nz);
+  c->b.sym.prod_wg = reinterpret_cast<uint32_t*>(base + o_pw);
   c->b.sym.work = reinterpret_cast<sp2::BsrWork*>(base + o_wk);
   c->b.ctr = reinterpret_cast<sp2::BsrCounters*>(base + o_ct);
   c->b.n = n;
@@ -1345,6 +1357,12 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   in.prm.max_iter = opt.max_iter;
   in.prm.norm = opt.norm;
   in.nbk = nb;
+  for (int k = 0; k < 2; ++k) {
+    in.brp[k] = c->b.m[k].row_ptr;
+    in.bcol[k] = c->b.m[k].col;
+    in.bflag[k] = c->b.m[k].flag;
+    in.bval[k] = c->b.m[k].val;
+  }
   if (opt.norm == SP2_NORM_MIXED) {
     // one block norm per block of the output pattern
     SP2_HIP(c, grow(c, c->d_blk, c->d_blk_cap,
@@ -1354,10 +1372,32 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
                     static_cast<size_t>(sp2::kLanczosMax) * nb * sizeof(double),
                     s));
     in.lz = c->d_lz;
-    for (int k = 0; k < 2; ++k) {
-      in.brp[k] = c->b.m[k].row_ptr;
-      in.bcol[k] = c->b.m[k].col;
-    }
+  }
+  c->spec_nchunks = 0;
+  if (opt.norm == SP2_NORM_SPECTRAL && n_occ != 0 && n_occ != n) {
+    // Lanczos scratch and one chunk (one block row) per 32 rows; the
+    // product's input vector is staged in LDS up to kSpecLdsVec entries
+    std::vector<int2> chunks;
+    for (int r = 0; r < n; r += sp2::kSpecRows) chunks.push_back(int2{0, r});
+    SP2_HIP(c, grow(c, c->d_spec, c->d_spec_cap,
+                    sp2::spec_doubles(static_cast<int>(n)) * sizeof(double), s));
+    SP2_HIP(c, grow(c, c->d_spec_chunks, c->d_spec_chunks_cap,
+                    chunks.size() * sizeof(int2), s));
+    SP2_HIP(c, grow(c, c->d_spec_ctl, c->d_spec_ctl_cap,
+                    (sp2::kMaxIter + 2) * sp2::kSpecCtl * sizeof(int32_t), s));
+    SP2_HIP(c, hipMemcpyAsync(c->d_spec_chunks, chunks.data(),
+                              chunks.size() * sizeof(int2),
+                              hipMemcpyHostToDevice, s));
+    c->spec_vec_cap = std::min(sp2::spec_ldq(static_cast<int>(n)), sp2::kSpecLdsVec);
+    const int gmax = sp2::spectral_max_grid(false, c->num_cus, c->spec_vec_cap);
+    if (gmax < 1)
+      return fail(c, SP2_HIP_ERROR, "spectral kernel: no co-resident grid",
+                  hipGetLastError());
+    c->spec_grid = std::min<int>(gmax, static_cast<int>(chunks.size()) + 1);
+    c->spec_nchunks = static_cast<int>(chunks.size());
+    in.sp = c->d_spec;
+    in.sp_ch0 = 0;
+    in.sp_nch = c->spec_nchunks;
   }
   SP2_HIP(c, grow(c, c->d_inst, c->d_inst_cap, sizeof(Instance), s));
   SP2_HIP(c, grow(c, c->d_part, c->d_part_cap, grid * 3 * sizeof(double), s));

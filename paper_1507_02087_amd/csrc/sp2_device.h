@@ -201,6 +201,11 @@ struct Instance {
   int pad_blk;
   const int32_t* brp[2];
   const int32_t* bcol[2];
+  // Block-sparse instance (null for dense ones): flags and 32 x 32 FP32
+  // values of the two iterate buffers, whose row pointers and columns are
+  // brp/bcol (step i reads buffer (i-1)&1)
+  const int32_t* bflag[2];
+  const float* bval[2];
   // Spectral norm (null unless prm.norm == 2): Lanczos scratch (spec_view)
   // and the instance's range in the chunk table of the spectral launch
   double* sp;
@@ -403,7 +408,11 @@ struct BsrSymbolic {
   int32_t* qcnt;      // nb
   int32_t* ucnt;      // nb
   int32_t* uptr;      // nb + 1
+  int32_t* nzrow;     // nb: flagged blocks per row of the iterate
   BsrWork* work;      // capacity
+  // block products of each numeric workgroup per step ((kMaxIter + 2) x
+  // grid), summed on the host after the run (no same-address atomics)
+  uint32_t* prod_wg;
 };
 
 struct BsrCounters {
@@ -411,8 +420,9 @@ struct BsrCounters {
   int32_t overflow;   // 1: capacity exceeded; 2: pattern not symmetric
   int32_t nupper;     // upper blocks of that pattern (work list length)
   int32_t pad;
-  // per step i: blocks of the pattern of X~_i, nonzero blocks of X~_{i-1},
-  // and block products X_IK X_JK^T computed
+  // per step i: blocks of the pattern of X~_i, flagged blocks of X~_{i-1},
+  // and block products X_IK X_JK^T computed (filled in on the host from
+  // BsrSymbolic::prod_wg)
   int32_t stored[kMaxIter + 2];
   int32_t nonzero[kMaxIter + 2];
   unsigned long long products[kMaxIter + 2];
@@ -429,7 +439,7 @@ hipError_t launch_bsr_symbolic(const BsrMat& A, int nb,
                                int32_t cap, BsrCounters* ctr,
                                const DevState* st, int iter, hipStream_t s);
 hipError_t launch_bsr_numeric(const BsrMat& A, const BsrMat& B,
-                              const BsrWork* work, BsrCounters* ctr,
+                              const BsrSymbolic& sym, BsrCounters* ctr,
                               const Instance* inst, int iter, int n,
                               double* part, int grid, hipStream_t s);
 hipError_t launch_bsr_f0(const double* F, const BsrMat& X, int nnzb,

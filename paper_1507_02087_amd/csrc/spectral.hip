@@ -1,5 +1,6 @@
 // Spectral norm of E = X~ - X~^2, the error e_i of Alg. 2 (sec. 2), for
-// every running instance of a batch, by Lanczos in FP64.
+// every running instance of a batch (dense) or of a block-sparse run, by
+// Lanczos in FP64.
 //
 // E is applied through two products with the stored iterate,
 // E q = X~ q - X~ (X~ q), so E itself is never formed and the estimate is the
@@ -138,6 +139,9 @@ struct SrcLds {
     a = lload(v + col);
     b = lload(v + col + 2);
   }
+  __device__ __forceinline__ double get1(int col) const {
+    return *(const __attribute__((address_space(3))) double*)(v + col);
+  }
 };
 struct SrcPlain {
   const double* v;
@@ -145,6 +149,7 @@ struct SrcPlain {
     a = gload<f64x2>(v + col);
     b = gload<f64x2>(v + col + 2);
   }
+  __device__ __forceinline__ double get1(int col) const { return gload<double>(v + col); }
 };
 struct SrcComb {
   const double* w;
@@ -157,6 +162,9 @@ struct SrcComb {
     const f64x2 qb = gload<f64x2>(q + col + 2);
     a = (wa - alpha * qa) * s;
     b = (wb - alpha * qb) * s;
+  }
+  __device__ __forceinline__ double get1(int col) const {
+    return (gload<double>(w + col) - alpha * gload<double>(q + col)) * s;
   }
 };
 
@@ -217,6 +225,50 @@ __device__ __forceinline__ void chunk_matvec(const T* __restrict__ X, int ld,
   for (int r = 0; r < kRowsPerWave; ++r) {
     const double t = wave_sum(acc[r]);
     if (lane == 0) out[wave * kRowsPerWave + r] = (r < nr) ? t : 0.0;
+  }
+}
+
+// The same product for a block-sparse instance (the chunk is one block row
+// I = row0 / 32 of the iterate in buffer k): out[r] = sum over the flagged
+// blocks (I, K) of sum_c X_IK[r][c] v[32 K + c], FP64 accumulation in block
+// order. Lane (h, c) takes column c of the rows of its half h; the block
+// columns of the row are read once into lanes and broadcast.
+template <typename Src>
+__device__ __forceinline__ void chunk_matvec_bsr(const Instance& in, int k,
+                                                 int row0, const Src& src,
+                                                 double* out) {
+  static_assert(kSpecRows == kBsrBlock, "one block row per chunk");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 31, h = lane >> 5;
+  const int I = row0 / kBsrBlock;
+  const int32_t* rp = in.brp[k];
+  const int q0 = rp[I], q1 = rp[I + 1];
+  double acc[kRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) acc[r] = 0.0;
+  for (int b0 = q0; b0 < q1; b0 += 64) {
+    const int qb = b0 + lane;
+    const int kc = (qb < q1 && in.bflag[k][qb] != 0) ? in.bcol[k][qb] : -1;
+    const int nb = min(64, q1 - b0);
+#pragma unroll 4
+    for (int t = 0; t < nb; ++t) {
+      const int K = __builtin_amdgcn_readlane(kc, t);
+      if (K < 0) continue;
+      const double vk = src.get1(K * kBsrBlock + c);
+      const float* blk = in.bval[k] + static_cast<size_t>(b0 + t) * kBsrBlock * kBsrBlock +
+                         (wave * kRowsPerWave) * kBsrBlock + c;
+#pragma unroll
+      for (int r = 0; r < kRowsPerWave; r += 2) {
+        const int rr = r + h;
+        acc[rr] = fma(static_cast<double>(gload<float>(blk + rr * kBsrBlock)), vk, acc[rr]);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    // rows of the other half contribute zero from this lane
+    const double t = wave_sum(((r & 1) == h) ? acc[r] : 0.0);
+    if (lane == 0) out[wave * kRowsPerWave + r] = (row0 + wave * kRowsPerWave + r < in.n) ? t : 0.0;
   }
 }
 
@@ -391,6 +443,7 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
       if (threadIdx.x == 0) v.nu[lc] = uu;
       if (j == kLanczosMax) continue;   // only beta_{j-1} is still needed
       const T* X = static_cast<const T*>(in.X[(iter - 1) & 1]);
+      const bool bsr = (in.bval[0] != nullptr);
       if (ldq <= a.vec_cap) {
         if (staged != ch.x) {
           __syncthreads();   // vs may still be read for the previous chunk
@@ -398,7 +451,12 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
           __syncthreads();
           staged = ch.x;
         }
-        chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcLds{vs}, rowv);
+        if (bsr)
+          chunk_matvec_bsr(in, (iter - 1) & 1, ch.y, SrcLds{vs}, rowv);
+        else
+          chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcLds{vs}, rowv);
+      } else if (bsr) {
+        chunk_matvec_bsr(in, (iter - 1) & 1, ch.y, SrcComb{v.w, qp, alpha, 1.0}, rowv);
       } else {
         chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y,
                         SrcComb{v.w, qp, alpha, 1.0}, rowv);
@@ -444,6 +502,7 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
       const double beta = sqrt(chunk_sum(v.nu, nch, red));
       const double inv = (beta > 0.0) ? 1.0 / beta : 0.0;
       const T* X = static_cast<const T*>(in.X[(iter - 1) & 1]);
+      const bool bsr = (in.bval[0] != nullptr);
       if (ldq <= a.vec_cap) {
         if (staged != ch.x) {
           __syncthreads();
@@ -451,10 +510,16 @@ __global__ __launch_bounds__(kThreads, 2) void spectral_kernel(SpecArgs a) {
           __syncthreads();
           staged = ch.x;
         }
-        chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcLds{vs}, rowv);
+        if (bsr)
+          chunk_matvec_bsr(in, (iter - 1) & 1, ch.y, SrcLds{vs}, rowv);
+        else
+          chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcLds{vs}, rowv);
       } else {
         // X~ (y / beta) = (X~ y) / beta
-        chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcPlain{v.y}, rowv);
+        if (bsr)
+          chunk_matvec_bsr(in, (iter - 1) & 1, ch.y, SrcPlain{v.y}, rowv);
+        else
+          chunk_matvec<T>(X, in.ld, in.n, ldq, ch.y, SrcPlain{v.y}, rowv);
         __syncthreads();
         if (threadIdx.x < kSpecRows) rowv[threadIdx.x] *= inv;
       }

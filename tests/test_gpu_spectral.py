@@ -218,12 +218,58 @@ def test_spectral_argument_errors():
     b = banded_instance(n=256, layers=4, seed=3)
     rp, ci, bl = to_bsr_blocks(b.F, 32)
     bctx = sp2.BsrContext(0)
-    with pytest.raises(sp2.SP2Error) as e:
-        bctx.init_bsr(256, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
-                      torch.from_numpy(np.ascontiguousarray(bl)).cuda(), b.lambda_min,
-                      b.lambda_max, b.n_occ, norm="spectral")
-    assert e.value.status == sp2.INVALID_ARG
+    # block-sparse runs take the spectral norm too, and report its history
+    bctx.init_bsr(256, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                  torch.from_numpy(np.ascontiguousarray(bl)).cuda(), b.lambda_min,
+                  b.lambda_max, b.n_occ, norm="spectral")
+    assert bctx.run() == sp2.OK
+    assert len(bctx.get_norm_history()) == bctx.get_info()[1]
+    with pytest.raises(sp2.SP2Error) as e:      # not a mixed-norm run
+        bctx.get_mixed_history()
+    assert e.value.status == sp2.BAD_STATE
     bctx.close()
+
+
+@pytest.mark.parametrize("n,layers,tau", [(1024, 12, 1e-6), (1000, 20, 1e-5)])
+def test_spectral_block_sparse(n, layers, tau):
+    """The spectral-norm stop on the block-sparse path (the Lanczos products
+    walk the flagged blocks of each block row of the stored iterate) against
+    the FP64 oracle run on the dense form with the same truncation and norm:
+    D, the e history (within the Lanczos cluster tolerance while the
+    trajectories agree) and the stop index (against the oracle with FP32
+    storage, whose rounding level sets where the error stagnates)."""
+    import torch
+    import paper_1507_02087_amd as sp2
+    b = banded_instance(n=n, layers=layers, seed=17 + n)
+    rp, ci, bl = to_bsr_blocks(b.F, 32)
+    print_case(f"spectral block-sparse n={n} layers={layers} tau={tau}")
+    ctx = sp2.BsrContext(0)
+    try:
+        ctx.init_bsr(n, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                     torch.from_numpy(np.ascontiguousarray(bl)).cuda(), b.lambda_min,
+                     b.lambda_max, b.n_occ, trunc_tau=tau, norm="spectral")
+        st = ctx.run()
+        D = ctx.get_density(as_fp64=True).cpu().numpy()
+        n_it, _, _ = ctx.get_info()
+        hist = ctx.get_history()
+        m = ctx.get_norm_history()
+    finally:
+        ctx.close()
+    Fd = b.F.toarray()
+    ref = oracle.sp2(Fd, b.lambda_min, b.lambda_max, b.n_occ, tau=tau, norm="spectral")
+    ref32 = oracle.sp2(Fd, b.lambda_min, b.lambda_max, b.n_occ, tau=tau, norm="spectral",
+                       working="fp32")
+    assert st == sp2.OK and ref.status == Status.OK
+    err = np.linalg.norm(D - ref.X) / math.sqrt(b.n_occ)
+    print(f"  n_gpu={n_it} n_oracle={ref.n} (fp32 storage {ref32.n}) err={err:.2e}",
+          flush=True)
+    assert err < 1e-4
+    assert abs(n_it - ref32.n) <= 2
+    assert len(m) == n_it + 1
+    u = U_EFF["fp32"]
+    for j, (x, y) in enumerate(zip(m, ref.v)):
+        if y > 1e-3 and hist["p"][:j + 1] == ref.p[:j + 1]:
+            assert abs(x - y) <= (CLUSTER_REL + 100 * (j + 1) * u) * y, (j, x, y)
 
 
 def test_spectral_krylov_and_timing():
