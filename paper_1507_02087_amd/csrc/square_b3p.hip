@@ -9,6 +9,7 @@ hipError_t launch_square_b3p(int id, const SquareArgs& a, int grid, hipStream_t 
     case 12: return launch_cfg<B3P_256_2x4>(a, grid, s);
     case 13: return launch_cfg<B3P_256_2x4_32>(a, grid, s);
     case 14: return launch_cfg<B3P_128_2x2>(a, grid, s);
+    case 16: return launch_cfg<B3P_256_4x4_32>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

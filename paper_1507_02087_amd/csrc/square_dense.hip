@@ -16,6 +16,7 @@ struct Presplit<CfgB3P<A, B, Cc, D>> {
   static constexpr int value = 1;
 };
 
+
 template <class C>
 constexpr KernelConfig describe(int precision, int occupancy,
                                 const char* name) {
@@ -36,6 +37,7 @@ const KernelConfig kConfigs[] = {
     SP2_DESCRIBE(B3S_256_2x4_16, 2, 1), SP2_DESCRIBE(B3S_128_2x2, 2, 2),
     SP2_DESCRIBE(B3P_256_2x4, 2, 1), SP2_DESCRIBE(B3P_256_2x4_32, 2, 1),
     SP2_DESCRIBE(B3P_128_2x2, 2, 2), SP2_DESCRIBE(F32_256_2x4, 1, 1),
+    SP2_DESCRIBE(B3P_256_4x4_32, 2, 1),
 };
 constexpr int kNumConfigs = sizeof(kConfigs) / sizeof(kConfigs[0]);
 
@@ -137,6 +139,7 @@ hipError_t launch_square(int id, const SquareArgs& a, int grid, hipStream_t s) {
     case 13: return launch_square_b3p(id, a, grid, s);
     case 14: return launch_square_b3p(id, a, grid, s);
     case 15: return launch_square_f32(id, a, grid, s);
+    case 16: return launch_square_b3p(id, a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -855,6 +855,11 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   // later slice reads). Branch-free loads let the compiler wait for just the
   // older register set before storing it, not for every load in flight.
   auto kc = [&](int kt) { return min(kt, k1 - 1) * C::BK; };
+  // Global loads run AHEAD - 1 slices ahead of their LDS store: two
+  // register sets for 8-wave workgroups; one for 16-wave workgroups, whose
+  // register budget (four waves per SIMD) has no room for a second and
+  // whose extra waves cover the latency instead.
+  constexpr int AHEAD = (C::THREADS > 512) ? 2 : 3;
   s0.load(Ah, Al, Bh, Bl, ld, k0 * C::BK, tid);
   sstore(s0, 0);
   // the scheduling fences keep each register set's loads together and in
@@ -862,7 +867,7 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   __builtin_amdgcn_sched_barrier(0);
   s0.load(Ah, Al, Bh, Bl, ld, kc(k0 + 1), tid);
   __builtin_amdgcn_sched_barrier(0);
-  s1.load(Ah, Al, Bh, Bl, ld, kc(k0 + 2), tid);
+  if constexpr (AHEAD == 3) s1.load(Ah, Al, Bh, Bl, ld, kc(k0 + 2), tid);
   __builtin_amdgcn_sched_barrier(0);
   __syncthreads();
   // one K slice: read the fragments of its first k step from buffer b,
@@ -877,7 +882,7 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
     fread(f, b, 0);
     __builtin_amdgcn_sched_barrier(0);
     sstore(st, b ^ 1);
-    st.load(Ah, Al, Bh, Bl, ld, kc(kt + 3), tid);
+    st.load(Ah, Al, Bh, Bl, ld, kc(kt + AHEAD), tid);
     mma(f);
 #pragma unroll
     for (int s8 = 8; s8 < C::KH; s8 += 8) {
@@ -889,11 +894,15 @@ __device__ __forceinline__ void mainloop_b3p(const StepCtx<float>& sc,
   };
   // pairs of slices, then an odd last one: no branch inside the loop body
   int kt = k0;
-  for (; kt + 1 < k1; kt += 2) {
-    step(kt, s0);
-    step(kt + 1, s1);
+  if constexpr (AHEAD == 3) {
+    for (; kt + 1 < k1; kt += 2) {
+      step(kt, s0);
+      step(kt + 1, s1);
+    }
+    if (kt < k1) step(kt, s0);
+  } else {
+    for (; kt < k1; ++kt) step(kt, s0);
   }
-  if (kt < k1) step(kt, s0);
 }
 
 // Tile-relative position of accumulator register j of fragment (m, n) held
@@ -1429,6 +1438,7 @@ using B3S_128_2x2 = CfgB3S<128, 2, 2, 32>;
 using B3P_256_2x4 = CfgB3P<256, 2, 4, 16>;
 using B3P_256_2x4_32 = CfgB3P<256, 2, 4, 32>;
 using B3P_128_2x2 = CfgB3P<128, 2, 2, 32>;
+using B3P_256_4x4_32 = CfgB3P<256, 4, 4, 32>;
 
 template <class C, int MODE, bool STRETCH>
 hipError_t launch_mode(const SquareArgs& a, int grid, hipStream_t s) {
