@@ -15,8 +15,10 @@
 //      K in P'(I) and P'(J) of X_IK X_JK^T (X_KJ = X_JK^T by symmetry) on
 //      v_mfma_f32_32x32x2_f32, then the same fused epilogue as the dense
 //      square (error, polynomial, truncation, FP64 traces) and the store of
-//      the block and of its transpose; persistent waves walk the upper
-//      blocks with a fixed stride, so the partial sums are deterministic.
+//      the block and of its transpose; each wave takes a fixed set of
+//      blocks, so the partial sums are deterministic.
+// Elements of a block are stored in the MFMA operand order of blk_off, so
+// that every load of a block row's operand reads contiguous memory.
 // Blocks that truncation empties stay in Q with flag 0 and are skipped by
 // the next step, so values are never compacted. The index kernel (nonzero
 // blocks per row, in column order) serves the extraction of the result.
@@ -282,36 +284,48 @@ __global__ __launch_bounds__(64) void bsr_symbolic_fill_kernel(
 // the work list per wave at a time. Workgroup b runs on XCD b % 8 (the grid
 // is a multiple of 8); XCD x takes the x-th contiguous eighth of the work
 // list (ordered by block row), so the blocks that neighbouring rows share
-// stay in its L2, and each of its workgroups a contiguous share of that
-// (about one block row). The workgroup's waves take the blocks of their
-// share in turn from an LDS counter, so a wave that drew a block with many
-// products (near the diagonal) does not hold up the others; each block's
-// partial sums go to a slot of its own and are added in block order, so
-// the sums do not depend on which wave took which block.
-// Per block: the flagged columns K of rows I and J (one per lane), the
-// common ones found by comparing each of row I's columns with every
-// column of row J (broadcast lane by lane), then the products X_IK X_JK^T
-// with the operands of the next product loaded during the current one's
-// MFMAs, and the old block X_IJ loaded straight into LDS beside them.
-__device__ __forceinline__ void load_block_frag(const float* val, int p, int r,
-                                                int h, floatx4 (&f)[4]) {
-  const float* b = val + static_cast<size_t>(p) * BE + r * BS + h * 16;
-  for (int u = 0; u < 4; ++u) f[u] = *gro(reinterpret_cast<const floatx4*>(b + 4 * u));
+// stay in its L2, and each of its workgroups a contiguous share of that;
+// wave w of a workgroup takes blocks w, w + 4, w + 8, ... of its share.
+// Every lane adds its elements' partial sums over the wave's blocks, then
+// the wave and the workgroup add theirs in a fixed order, so the sums do
+// not depend on timing.
+// Per block: the flagged columns K of rows I and J (one per lane, both rows
+// loaded at once), the common ones found by comparing each of row I's
+// columns with every column of row J (broadcast lane by lane), then the
+// products X_IK X_JK^T with the operands of the next product loaded during
+// the current one's MFMAs. The old block is read as its stored transpose
+// X_JI (rows of X_JI are columns of X_IJ, which is what each lane's
+// accumulator holds) into registers while the products run. The work
+// entry of the wave's next block is loaded at the start of this one, its
+// row extents during this one's epilogue.
+__device__ __forceinline__ void load_block_frag(const float* val, int p, int lane,
+                                                floatx4 (&f)[4]) {
+  const float* b = val + static_cast<size_t>(p) * BE + 4 * lane;
+  for (int u = 0; u < 4; ++u) f[u] = *gro(reinterpret_cast<const floatx4*>(b + 256 * u));
 }
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-constexpr int kSlots = 64;   // blocks per batch of a workgroup's share
+// Row stride of the LDS tile that transposes an output block: 36 floats keep
+// every 16-byte row segment aligned, and the 16 lanes of a quarter-wave read
+// rows m at 36 m, which fall on 16 distinct groups of four of the 64 banks.
+constexpr int kTileLd = 36;
 
 __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
     BsrMat A, BsrMat B, const BsrWork* __restrict__ work, uint32_t* prod_wg,
     BsrCounters* ctr, const Instance* inst, int iter, int n, double* part) {
+  __shared__ double wsum[4][3];
   __shared__ unsigned long long shp[4];
-  __shared__ __attribute__((aligned(16))) float old_lds[4][BE];
-  __shared__ double slot[kSlots][3];
-  __shared__ int next_item;
-  const Instance& in = inst[0];
-  const DevState* st = in.st;
+  // per wave: the output block, row-major with rows padded to 36 floats, to
+  // turn the accumulator's columns into the storage order's rows
+  __shared__ __attribute__((aligned(16))) float tile[4][BS * kTileLd];
+  // The instance and its state are read as scalars through the constant
+  // address space (neither changes during the launch). Through generic
+  // pointers they would be FLAT loads, and while one of those is pending the
+  // compiler cannot count vector loads in order, so every wait in the
+  // product loop below would wait for all loads in flight.
+  const auto* in = cro(inst);
+  const auto* st = cro(in->st);
   if (st->done) return;
   if (ctr->overflow) {
     // No product this step: non-finite partial sums make the finalize step
@@ -325,7 +339,20 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
     return;
   }
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = uni(threadIdx.x >> 6);
+  // The step squares the stored Y = a X~ + c I (OpMap); X_i = S or 2 Y - S,
+  // the error of X~ from Y and S, and the stored output is the next step's
+  // matrix an X~_i + cn I. These and the truncation threshold are read once.
+  const bool p1 = st->p[iter] != 0;
+  const StepCoef k{st->ecoef[0], st->ecoef[1], st->ecoef[2], st->ecoef[3],
+                   st->ecoef[4]};
+  const bool stretch = st->stretch != 0;
+  const float ka = p1 ? 1.f : -1.f, kb = p1 ? 0.f : 2.f;
+  const double tau = in->tau;
+  // the largest float below tau: for a float x, |x| < tau <=> |x| <= tf
+  float tf = static_cast<float>(tau);
+  if (tf > 0.f && static_cast<double>(tf) >= tau) tf = __int_as_float(__float_as_int(tf) - 1);
+  float* const blk = in->blk;
   const int total = ctr->nupper;
   const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
   const int x = blockIdx.x % nx;
@@ -334,25 +361,36 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
   const int u_hi = static_cast<int>(static_cast<int64_t>(total) * (x + 1) / nx);
   const int w_lo = u_lo + static_cast<int>(static_cast<int64_t>(u_hi - u_lo) * lb / gx);
   const int w_hi = u_lo + static_cast<int>(static_cast<int64_t>(u_hi - u_lo) * (lb + 1) / gx);
-  double tsum[3] = {0.0, 0.0, 0.0};   // thread 0: the workgroup's sums
-  // the largest float below tau: for a float x, |x| < tau <=> |x| <= tf
-  const double tau_ = in.tau;
-  float tf = static_cast<float>(tau_);
-  if (tf > 0.f && static_cast<double>(tf) >= tau_) tf = __int_as_float(__float_as_int(tf) - 1);
+  double sv = 0.0, st1 = 0.0, st2 = 0.0;   // this lane's partial sums
   unsigned long long nprod = 0;
+  // the lane's entry of a row chunk: its column if flagged, else `none`.
+  // Lanes past the row read position 0 (always valid) and discard it, so the
+  // loads need no branch and the two rows' loads are all in flight at once.
   auto first_cols = [&](int lo, int hi, int none) {
-    return (lo + lane < hi && A.flag[lo + lane] != 0) ? A.col[lo + lane] : none;
+    const bool ok = lo + lane < hi;
+    const int i = ok ? lo + lane : 0;
+    const int f = A.flag[i];
+    const int c = A.col[i];
+    return (ok && f != 0) ? c : none;
   };
-  for (int bs = w_lo; bs < w_hi; bs += kSlots) {
-    const int be = min(bs + kSlots, w_hi);
-    if (threadIdx.x == 0) next_item = bs;
-    __syncthreads();
-    for (;;) {
-    int u = 0;
-    if (lane == 0) u = atomicAdd(&next_item, 1);
-    u = uni(__shfl(u, 0, 64));
-    if (u >= be) break;
-    double sv = 0.0, st1 = 0.0, st2 = 0.0;
+  // work list and row pointers of the old iterate: read-only here, read as
+  // scalars (so their waits do not include the vector stores in flight)
+  const auto* wl = cro(work);
+  const auto* rp = cro(A.row_ptr);
+  auto work_at = [&](int i) {
+    return BsrWork{wl[i].q, wl[i].qT, wl[i].I, wl[i].J};
+  };
+  int u = w_lo + wave;
+  BsrWork wk{0, 0, 0, 0};
+  int i0 = 0, i1 = 0, j0 = 0, j1 = 0;
+  if (u < w_hi) {
+    wk = work_at(u);
+    i0 = rp[wk.I];
+    i1 = rp[wk.I + 1];
+    j0 = rp[wk.J];
+    j1 = rp[wk.J + 1];
+  }
+  for (; u < w_hi; u += 4) {
     // The lane's row and half, made opaque per block so that the compiler
     // does not hoist the 16 elements' lane masks and addresses out of the
     // loop (they would not fit in registers).
@@ -360,34 +398,48 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
     asm volatile("" : "+v"(lr));
     const int r = lr & 31, h = lr >> 5;
     // wave-uniform values (kept in scalar registers)
-    const BsrWork wk = work[u];
     const int q = uni(wk.q), qT = uni(wk.qT), I = uni(wk.I), J = uni(wk.J);
+    const int ri0 = uni(i0), ri1 = uni(i1), rj0 = uni(j0), rj1 = uni(j1);
     const bool diag = (I == J);
-    const int i0 = uni(A.row_ptr[I]), i1 = uni(A.row_ptr[I + 1]);
-    const int j0 = uni(A.row_ptr[J]), j1 = uni(A.row_ptr[J + 1]);
+    const int un = u + 4;
+    BsrWork wn{0, 0, 0, 0};
+    if (un < w_hi) wn = work_at(un);
+    // first 64 flagged columns of both rows
+    const int KI0 = first_cols(ri0, ri1, -1);
+    const int KJ0 = first_cols(rj0, rj1, -2);
+    // the old block's transpose X_JI, if row J holds it flagged
+    int po = -1;
+    for (int d0 = rj0; d0 < rj1; d0 += 64) {
+      const int KJ = (d0 == rj0) ? KJ0 : first_cols(d0, rj1, -2);
+      const unsigned long long mo = __ballot(KJ == I);
+      if (mo) {
+        po = __builtin_amdgcn_readlane(d0 + lane, __ffsll(static_cast<long long>(mo)) - 1);
+        break;
+      }
+    }
+    // the old block's elements of this lane: X_IJ[m][r] = X_JI[r][m] for
+    // m = 8 a + 4 h + e are four consecutive floats of the stored X_JI per a
+    // (one coalesced 16-byte load each), in flight during the products
+    floatx4 xo4[4];
+    if (po >= 0) {
+      const float* ob = A.val + static_cast<size_t>(po) * BE;
+      for (int a = 0; a < 4; ++a)
+        xo4[a] = *gro(reinterpret_cast<const floatx4*>(ob + ((2 * a + h) & 3) * 256 +
+                                                       (r + 32 * (a >> 1)) * 4));
+    } else {
+      for (int a = 0; a < 4; ++a) xo4[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
     floatx16 acc;
     for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-    int po = -1;             // position of the old block X_IJ, if row I holds it
-    for (int c0 = i0; c0 < i1; c0 += 64) {
-      const int K = first_cols(c0, i1, -1);
+    for (int c0 = ri0; c0 < ri1; c0 += 64) {
+      const int K = (c0 == ri0) ? KI0 : first_cols(c0, ri1, -1);
       const bool vi = K >= 0;
       const int pI = c0 + lane;
-      const unsigned long long mo = __ballot(K == J);
-      if (mo) {
-        po = __builtin_amdgcn_readlane(pI, __ffsll(static_cast<long long>(mo)) - 1);
-        // the old block goes straight to this wave's LDS area (four loads
-        // of 64 x 16 bytes) while the products run
-        const char* gb = reinterpret_cast<const char*>(A.val + static_cast<size_t>(po) * BE);
-        for (int kq = 0; kq < 4; ++kq)
-          __builtin_amdgcn_global_load_lds(
-              (const __attribute__((address_space(1))) void*)(gb + kq * 1024 + 16 * lane),
-              (__attribute__((address_space(3))) void*)(&old_lds[wave][kq * 256]), 16, 0, 0);
-      }
       int pJ = -1;
-      for (int d0 = j0; d0 < j1; d0 += 64) {
-        const int KJ = first_cols(d0, j1, -2);
+      for (int d0 = rj0; d0 < rj1; d0 += 64) {
+        const int KJ = (d0 == rj0) ? KJ0 : first_cols(d0, rj1, -2);
         const int PJ = d0 + lane;
-        const int m = min(64, j1 - d0);
+        const int m = min(64, rj1 - d0);
         for (int t = 0; t < m; ++t) {
           const int kt = __builtin_amdgcn_readlane(KJ, t);
           const int pt = __builtin_amdgcn_readlane(PJ, t);
@@ -395,55 +447,68 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
         }
       }
       unsigned long long mask = __ballot(vi && pJ >= 0);
-      nprod += __popcll(mask);
-      // products in mask order; the next product's blocks load while the
-      // current one's MFMAs run
-      if (!mask) continue;
-      floatx4 fa[4], fb[4];
+      const int np = __popcll(mask);
+      nprod += np;
+      if (!np) continue;
+      // Products in mask order, in pairs, through two operand sets: while
+      // one set's MFMAs run, the other set's loads are in flight. Every pair
+      // but the last is a loop iteration that also loads the next pair;
+      // loads past the last product repeat its blocks. With a single exit
+      // from the loop and the same loads outstanding on every path, each
+      // wait covers only the set it uses. (The empty asm with a memory
+      // clobber keeps each set's loads where they are issued, and the
+      // scheduling barrier keeps the other set's MFMAs after them.)
       int src = __ffsll(static_cast<long long>(mask)) - 1;
-      mask &= mask - 1;
-      load_block_frag(A.val, __builtin_amdgcn_readlane(pI, src), r, h, fa);
-      load_block_frag(A.val, __builtin_amdgcn_readlane(pJ, src), r, h, fb);
-      for (;;) {
-        const bool more = mask != 0;
-        floatx4 na[4], nb[4];
-        if (more) {
+      auto next_src = [&]() {
+        if (mask) {
           src = __ffsll(static_cast<long long>(mask)) - 1;
           mask &= mask - 1;
-          load_block_frag(A.val, __builtin_amdgcn_readlane(pI, src), r, h, na);
-          load_block_frag(A.val, __builtin_amdgcn_readlane(pJ, src), r, h, nb);
         }
+        return src;
+      };
+      auto load_pair = [&](int sl, floatx4 (&xa)[4], floatx4 (&xb)[4]) {
+        load_block_frag(A.val, __builtin_amdgcn_readlane(pI, sl), lr, xa);
+        load_block_frag(A.val, __builtin_amdgcn_readlane(pJ, sl), lr, xb);
+      };
+      auto mfma16 = [&](const floatx4 (&xa)[4], const floatx4 (&xb)[4]) {
         for (int s = 0; s < 16; ++s)
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[s >> 2][s & 3],
-                                                     fb[s >> 2][s & 3], acc,
-                                                     0, 0, 0);
-        if (!more) break;
-        for (int v = 0; v < 4; ++v) {
-          fa[v] = na[v];
-          fb[v] = nb[v];
-        }
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa[s >> 2][s & 3], xb[s >> 2][s & 3],
+                                                     acc, 0, 0, 0);
+      };
+      floatx4 fa[4], fb[4], ga[4], gb[4];
+      load_pair(next_src(), fa, fb);
+      load_pair(next_src(), ga, gb);
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_sched_barrier(0);
+      const int pairs = (np + 1) >> 1;
+      for (int pp = 1; pp < pairs; ++pp) {
+        mfma16(fa, fb);
+        load_pair(next_src(), fa, fb);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        mfma16(ga, gb);
+        load_pair(next_src(), ga, gb);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
       }
+      mfma16(fa, fb);
+      if (!(np & 1)) mfma16(ga, gb);
     }
+    // acc[j] is element (m, r) of S_IJ, m = 8 (j/4) + 4 h + j%4
     float xo[16];
-    if (po >= 0) {
-      __builtin_amdgcn_s_waitcnt(0);   // this wave's old block is in LDS
-      const float* ol = &old_lds[wave][4 * h * BS + r];
-      for (int j = 0; j < 16; ++j) xo[j] = ol[(8 * (j >> 2) + (j & 3)) * BS];
-    } else {
-      for (int j = 0; j < 16; ++j) xo[j] = 0.f;
+    for (int a = 0; a < 4; ++a)
+      for (int e = 0; e < 4; ++e) xo[4 * a + e] = xo4[a][e];
+    // the next block's row extents load during this epilogue
+    int ni0 = 0, ni1 = 0, nj0 = 0, nj1 = 0;
+    if (un < w_hi) {
+      ni0 = rp[wn.I];
+      ni1 = rp[wn.I + 1];
+      nj0 = rp[wn.J];
+      nj1 = rp[wn.J + 1];
     }
-    // the step squares the stored Y = a X~ + c I (OpMap); X_i = S or 2 Y - S,
-    // the error of X~ from Y and S, and the stored output is the next step's
-    // matrix an X~_i + cn I
-    const bool p1 = st->p[iter] != 0;
-    const StepCoef k{st->ecoef[0], st->ecoef[1], st->ecoef[2], st->ecoef[3],
-                     st->ecoef[4]};
-    const bool stretch = st->stretch != 0;
-    const float ka = p1 ? 1.f : -1.f, kb = p1 ? 0.f : 2.f;
-    const double tau = in.tau;
-    // Epilogue (acc[j] is element (m, r) of S_IJ, m = 8 (j/4) + 4 h + j%4).
     float* out = B.val + static_cast<size_t>(q) * BE;
     float* outT = B.val + static_cast<size_t>(qT) * BE;
+    float* const tl = &tile[wave][0];
     bool nz = false;
     double bsq = 0.0;   // squared Frobenius norm of this block of X~ - S
     float xs[16];
@@ -467,51 +532,56 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
       sv += 2.0 * e2;
       st2 += 2.0 * x2;
       bsq = e2;
-    }
-    if (diag)
-    for (int j = 0; j < 16; ++j) {
-      const int m = 8 * (j >> 2) + 4 * h + (j & 3);   // row in the block
-      const int c = r;                                // column in the block
-      xs[j] = 0.f;
-      if (m > c) continue;
-      const float s = acc[j];
-      // identity terms only inside the matrix proper
-      const bool on = (diag && m == c && I * BS + m < n);
-      const double d = __builtin_fma(k.es, static_cast<double>(s),
-                                     k.ey * static_cast<double>(xo[j])) +
-                       (on ? k.ei : 0.0);
-      const double w = (diag && m == c) ? 1.0 : 2.0;
-      sv += w * d * d;
-      bsq += diag ? w * d * d : d * d;
-      float xn = __builtin_fmaf(kb, xo[j], ka * s);
-      double xd = static_cast<double>(xn);
-      if (fabs(xd) < tau) {
-        xn = 0.f;
-        xd = 0.0;
+      // the transposed block: elements (r, m) for four consecutive m are
+      // consecutive in storage
+      for (int a = 0; a < 4; ++a) {
+        floatx4 v4;
+        for (int e = 0; e < 4; ++e) v4[e] = xs[4 * a + e];
+        *grw(reinterpret_cast<floatx4*>(outT + ((2 * a + h) & 3) * 256 + (r + 32 * (a >> 1)) * 4)) = v4;
       }
-      st2 += w * xd * xd;
-      if (diag && m == c) st1 += xd;
-      if (stretch) xn = static_cast<float>(__builtin_fma(k.an, xd, on ? k.cn : 0.0));
-      nz = nz || (xn != 0.f);   // the stored block, the next step's operand
-      xs[j] = xn;
-    }
-    float* ob = out + 4 * h * BS + r;           // element (4 h, r)
-    float* obT = outT + r * BS + 4 * h;         // element (r, 4 h)
-    if (diag) {
-      // upper elements and their mirror images
+      // the block itself through the tile: element (m, r) at m * 36 + r
+      for (int j = 0; j < 16; ++j) tl[(8 * (j >> 2) + 4 * h + (j & 3)) * kTileLd + r] = xs[j];
+    } else {
+      for (int j = 0; j < 16; ++j) {
+        const int m = 8 * (j >> 2) + 4 * h + (j & 3);   // row in the block
+        const int c = r;                                // column in the block
+        xs[j] = 0.f;
+        if (m > c) continue;
+        const float s = acc[j];
+        // identity terms only inside the matrix proper
+        const bool on = (m == c && I * BS + m < n);
+        const double d = __builtin_fma(k.es, static_cast<double>(s),
+                                       k.ey * static_cast<double>(xo[j])) +
+                         (on ? k.ei : 0.0);
+        const double w = (m == c) ? 1.0 : 2.0;
+        sv += w * d * d;
+        bsq += w * d * d;
+        float xn = __builtin_fmaf(kb, xo[j], ka * s);
+        double xd = static_cast<double>(xn);
+        if (fabs(xd) < tau) {
+          xn = 0.f;
+          xd = 0.0;
+        }
+        st2 += w * xd * xd;
+        if (m == c) st1 += xd;
+        if (stretch) xn = static_cast<float>(__builtin_fma(k.an, xd, on ? k.cn : 0.0));
+        nz = nz || (xn != 0.f);   // the stored block, the next step's operand
+        xs[j] = xn;
+      }
+      // upper elements and their mirror images, through the tile
       for (int j = 0; j < 16; ++j) {
         const int m = 8 * (j >> 2) + 4 * h + (j & 3);
-        const int o = 8 * (j >> 2) + (j & 3);
-        if (m <= r) *grw(ob + o * BS) = xs[j];
-        if (m < r) *grw(obT + o) = xs[j];
+        if (m <= r) tl[m * kTileLd + r] = xs[j];
+        if (m < r) tl[r * kTileLd + m] = xs[j];
       }
-    } else {
-      for (int j = 0; j < 16; ++j) *grw(ob + (8 * (j >> 2) + (j & 3)) * BS) = xs[j];
-      // the transposed block: four consecutive elements of row r per store
-      for (int g = 0; g < 4; ++g) {
-        floatx4 v4;
-        for (int e = 0; e < 4; ++e) v4[e] = xs[4 * g + e];
-        *grw(reinterpret_cast<floatx4*>(obT + 8 * g)) = v4;
+    }
+    // Storage panel u of the block is one contiguous 1 KiB: lane l = m + 32 g
+    // writes row m, columns 16 g + 4 u .. + 3 (a 16-byte read of the tile).
+    {
+      const int m = lr & 31, g = lr >> 5;
+      for (int u4 = 0; u4 < 4; ++u4) {
+        const floatx4 v = *reinterpret_cast<const floatx4*>(tl + m * kTileLd + 16 * g + 4 * u4);
+        *grw(reinterpret_cast<floatx4*>(out + 256 * u4 + 4 * lr)) = v;
       }
     }
     const int any = __any(nz) ? 1 : 0;
@@ -519,39 +589,36 @@ __global__ __launch_bounds__(256, 4) void bsr_numeric_kernel(
       B.flag[q] = any;
       B.flag[qT] = any;
     }
-    if (in.blk) {
+    if (blk) {
       // mixed norm: one value per block of the output pattern
       bsq = wave_sum(bsq);
       if (lane == 0) {
         const float bn = static_cast<float>(sqrt(bsq));
-        *grw(in.blk + q) = bn;
-        *grw(in.blk + qT) = bn;
+        *grw(blk + q) = bn;
+        *grw(blk + qT) = bn;
       }
     }
-    // this block's partial sums in its slot
-    sv = wave_sum(sv);
-    st1 = wave_sum(st1);
-    st2 = wave_sum(st2);
-    if (lane == 0) {
-      slot[u - bs][0] = sv;
-      slot[u - bs][1] = st1;
-      slot[u - bs][2] = st2;
-    }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int t = 0; t < be - bs; ++t)
-        for (int v = 0; v < 3; ++v) tsum[v] += slot[t][v];
-    __syncthreads();   // the slots and the counter are reused
+    wk = wn;
+    i0 = ni0;
+    i1 = ni1;
+    j0 = nj0;
+    j1 = nj1;
   }
-  if (lane == 0) shp[wave] = nprod;
+  sv = wave_sum(sv);
+  st1 = wave_sum(st1);
+  st2 = wave_sum(st2);
+  if (lane == 0) {
+    wsum[wave][0] = sv;
+    wsum[wave][1] = st1;
+    wsum[wave][2] = st2;
+    shp[wave] = nprod;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     prod_wg[static_cast<size_t>(iter) * gridDim.x + blockIdx.x] =
         static_cast<uint32_t>(shp[0] + shp[1] + shp[2] + shp[3]);
-    part[3 * blockIdx.x + 0] = tsum[0];
-    part[3 * blockIdx.x + 1] = tsum[1];
-    part[3 * blockIdx.x + 2] = tsum[2];
+    for (int v = 0; v < 3; ++v)
+      part[3 * blockIdx.x + v] = ((wsum[0][v] + wsum[1][v]) + wsum[2][v]) + wsum[3][v];
   }
 }
 
@@ -594,7 +661,7 @@ __global__ __launch_bounds__(256) void bsr_f0_kernel(
             ? static_cast<float>(__builtin_fma(m1.a, xd,
                                                (gi == gj && gi < n) ? m1.c : 0.0))
             : xs;
-    X.val[static_cast<size_t>(q) * BE + e] = xst;
+    X.val[static_cast<size_t>(q) * BE + blk_off(m, c)] = xst;
     t2 += xd * xd;
     if (gi == gj) t1 += xd;
     nz = nz || (xst != 0.f);
@@ -638,7 +705,7 @@ __global__ __launch_bounds__(256) void bsr_gather_kernel(
       const int i = e / BS, j = e % BS;
       const bool on = dblk && i == j && brow[p] * BS + i < n;
       out[static_cast<size_t>(b) * BE + e] = static_cast<To>(
-          (static_cast<double>(src[e]) - (on ? m.c : 0.0)) / m.a);
+          (static_cast<double>(src[blk_off(i, j)]) - (on ? m.c : 0.0)) / m.a);
     }
   }
 }
@@ -657,7 +724,8 @@ __global__ __launch_bounds__(256) void bsr_to_dense_kernel(
       const int gi = I * BS + e / BS, gj = J * BS + e % BS;
       if (gi < n && gj < n)
         D[gi * ldd + gj] = static_cast<To>(
-            (static_cast<double>(src[e]) - (gi == gj ? m.c : 0.0)) / m.a);
+            (static_cast<double>(src[blk_off(e / BS, e % BS)]) - (gi == gj ? m.c : 0.0)) /
+            m.a);
     }
   }
   (void)nb;

@@ -27,6 +27,12 @@ template <typename T>
 __device__ __forceinline__ __attribute__((address_space(1))) T* grw(T* p) {
   return (__attribute__((address_space(1))) T*)(p);
 }
+// Read-only data that no thread writes during the launch, read through the
+// constant address space: uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cro(const T* p) {
+  return (const __attribute__((address_space(4))) T*)(p);
+}
 
 // Largest number of squares one run may compute (public SP2_MAX_ITER_LIMIT).
 constexpr int kMaxIter = 200;
@@ -378,11 +384,21 @@ constexpr int kBsrBlock = 32;
 constexpr int kMaxBlockCols = 2048;   // block rows/columns: n <= 65536
 
 // One block-sparse iterate: both triangles stored, columns sorted per row.
+// Storage order of the 1024 elements of a block: four panels of 256 floats;
+// panel u holds, for each of the 64 (row m, half g) pairs in the order
+// m + 32 g, the four columns 16 g + 4 u .. 16 g + 4 u + 3. Lane l = m + 32 g
+// of a wave thus reads the 16 elements of its row and half as four 16-byte
+// loads at u * 256 + 4 l, each instruction one contiguous 1 KiB, which is
+// the operand layout of the 32 x 32 x 2 MFMA over a block row.
+__host__ __device__ constexpr int blk_off(int m, int c) {
+  return ((c & 15) >> 2) * 256 + (m + 32 * (c >> 4)) * 4 + (c & 3);
+}
+
 struct BsrMat {
   int32_t* row_ptr;   // nb + 1
   int32_t* col;       // capacity
   int32_t* brow;      // capacity: block row of each stored block
-  float* val;         // capacity * 32 * 32, row-major blocks
+  float* val;         // capacity * 32 * 32, element (m, c) at blk_off(m, c)
   int32_t* flag;      // capacity: 1 if the block holds a nonzero
 };
 

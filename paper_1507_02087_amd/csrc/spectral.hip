@@ -255,12 +255,12 @@ __device__ __forceinline__ void chunk_matvec_bsr(const Instance& in, int k,
       const int K = __builtin_amdgcn_readlane(kc, t);
       if (K < 0) continue;
       const double vk = src.get1(K * kBsrBlock + c);
-      const float* blk = in.bval[k] + static_cast<size_t>(b0 + t) * kBsrBlock * kBsrBlock +
-                         (wave * kRowsPerWave) * kBsrBlock + c;
+      const float* blk = in.bval[k] + static_cast<size_t>(b0 + t) * kBsrBlock * kBsrBlock;
 #pragma unroll
       for (int r = 0; r < kRowsPerWave; r += 2) {
         const int rr = r + h;
-        acc[rr] = fma(static_cast<double>(gload<float>(blk + rr * kBsrBlock)), vk, acc[rr]);
+        acc[rr] = fma(static_cast<double>(gload<float>(blk + blk_off(wave * kRowsPerWave + rr, c))),
+                      vk, acc[rr]);
       }
     }
   }
