@@ -378,7 +378,7 @@ def bench_bsr(args):
                      {"bound": "hbm", "achieved": round(achieved_gbps, 1), "peak": 8000.0,
                       "unit": "GB/s", "frac": round(achieved_gbps / 8000.0, 4)}) | {
                      "traffic": traffic,
-                     "kernel": "block-sparse step (symbolic count, scan, fill + numeric kernels)",
+                     "kernel": "block-sparse step (symbolic count, fill + numeric kernels)",
                      "per_launch_flops": round(flops / max(1, len(kt)), 0),
                      "per_launch_bytes": round(bytes_min / max(1, len(kt)), 0),
                      "hbm_min_bytes_gbps": round(achieved_gbps, 1),

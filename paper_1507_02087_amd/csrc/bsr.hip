@@ -7,10 +7,9 @@
 //
 // One step, X~_{i-1} (pattern P, some blocks flagged zero) -> X~_i:
 //   1. symbolic product: the pattern Q = P' P' + P' + diag (P': the flagged
-//      blocks) per block row from an LDS bitmap over the block columns, an
-//      exclusive scan of the row counts, and a fill of the sorted column
-//      indices and of the list of upper blocks (I, J >= I) with the
-//      position of each one's transpose;
+//      blocks) per block row from an LDS bitmap over the block columns, then
+//      a fill of the row starts, the sorted column indices and the list of
+//      upper blocks (I, J >= I) with the position of each one's transpose;
 //   2. numeric: one wave per upper block (I, J) of Q, S_IJ = sum over
 //      K in P'(I) and P'(J) of X_IK X_JK^T (X_KJ = X_JK^T by symmetry) on
 //      v_mfma_f32_32x32x2_f32, then the same fused epilogue as the dense
@@ -179,84 +178,113 @@ __global__ __launch_bounds__(kCountThreads) void bsr_symbolic_count_kernel(
   }
 }
 
-// (2b) Row pointers of Q and of the upper work list; flags an overflow when
-// Q exceeds the capacity.
-__global__ __launch_bounds__(kScanThreads) void bsr_symbolic_scan_kernel(
-    BsrSymbolic sym, int nb, int32_t* row_ptr, int32_t cap, BsrCounters* ctr,
-    const DevState* st, int iter) {
-  __shared__ int32_t cnt[2 * kScanThreads];
-  __shared__ int32_t sh[kScanThreads];
-  if (st->done) return;
-  for (int r = threadIdx.x; r < nb; r += kScanThreads) cnt[r] = sym.qcnt[r];
-  __syncthreads();
-  block_exclusive_scan(cnt, nb, row_ptr, sh);
-  __syncthreads();
-  for (int r = threadIdx.x; r < nb; r += kScanThreads) cnt[r] = sym.ucnt[r];
-  __syncthreads();
-  block_exclusive_scan(cnt, nb, sym.uptr, sh);
-  __syncthreads();
-  // flagged blocks of the iterate (statistics)
-  int nz = 0;
-  for (int r = threadIdx.x; r < nb; r += kScanThreads) nz += sym.nzrow[r];
-  for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = nz;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int nzt = 0;
-    for (int w = 0; w < kScanThreads / 64; ++w) nzt += sh[w];
-    const int total = row_ptr[nb];
-    ctr->nnzb = total;
-    ctr->nupper = sym.uptr[nb];
-    ctr->stored[iter] = total;
-    ctr->nonzero[iter] = nzt;
-    if (total > cap) ctr->overflow = 1;
-  }
-}
-
-// (2c) Sorted column indices (and block rows) of Q from the bitmaps, and the
+// (2b) Sorted column indices (and block rows) of Q from the bitmaps, and the
 // upper work list: for each block (I, J >= I) its position, the position of
-// (J, I) (row pointer of J plus the rank of I among the columns of row J,
-// from J's bitmap word and its prefix popcount), I and J. One wave per row.
+// (J, I) (start of row J plus the rank of I among the columns of row J, from
+// J's bitmap word and its prefix popcount), I and J. One wave per row. The
+// row starts of Q are exclusive sums of the row counts; every workgroup
+// forms them itself in LDS (integer sums, exact in any order) rather than
+// waiting for a separate scan launch, and so also knows the totals: a
+// pattern over capacity stops every workgroup before it writes anything.
+// Workgroup 0 records the totals and the statistics for the host.
+static_assert(kMaxBlockCols <= 64 * 32, "a row's bitmap is at most one word per lane");
 __global__ __launch_bounds__(64) void bsr_symbolic_fill_kernel(
-    BsrSymbolic sym, int nb, int nbw, BsrMat Q, BsrCounters* ctr,
-    const DevState* st) {
+    BsrSymbolic sym, int nb, int nbw, BsrMat Q, int32_t cap, BsrCounters* ctr,
+    const DevState* st, int iter) {
   __shared__ int32_t cols[kMaxBlockCols];
-  if (st->done || ctr->overflow) return;
+  __shared__ int32_t pre[kMaxBlockCols + 1];
+  if (st->done) return;
   const int I = blockIdx.x;
   const int lane = threadIdx.x;
-  const int row0 = Q.row_ptr[I];
+  // this row's bitmap words (nbw <= 64: one per lane) and the prefix
+  // popcount at the diagonal's word, loaded with the row counts below
+  const int wi = I >> 5;
   const uint32_t* brow_bits = sym.bitmap + static_cast<size_t>(I) * nbw;
-  int base = 0;
-  for (int w0 = 0; w0 < nbw; w0 += 64) {
-    const int w = w0 + lane;
-    const uint32_t bits = (w < nbw) ? brow_bits[w] : 0u;
-    const int c = __popc(bits);
-    int incl = c;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int v = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += v;
+  const uint32_t bits = (lane < nbw) ? brow_bits[lane] : 0u;
+  const int wpre_i = sym.wpre[static_cast<size_t>(I) * nbw + wi];
+  // exclusive prefix sums of the stored blocks per row (pre) and the upper
+  // blocks before row I (u0): lane l takes rows l * per .. l * per + per - 1
+  // (all its loads in flight at once), then one scan over the lanes' sums
+  constexpr int kPer = kMaxBlockCols / 64;
+  const int per = (nb + 63) / 64;
+  const int r0 = lane * per;
+  int v[kPer];
+  int sum = 0, ub = 0, ut = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int r = r0 + k;
+    const bool ok = k < per && r < nb;
+    v[k] = ok ? sym.qcnt[r] : 0;
+    const int uc = ok ? sym.ucnt[r] : 0;
+    sum += v[k];
+    ut += uc;
+    ub += (ok && r < I) ? uc : 0;
+  }
+  int incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int x = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += x;
+  }
+  int run = incl - sum;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int r = r0 + k;
+    if (k < per && r < nb) pre[r] = run;
+    run += v[k];
+  }
+  const int base = __shfl(incl, 63, 64);
+  for (int off = 32; off > 0; off >>= 1) {
+    ub += __shfl_xor(ub, off, 64);
+    ut += __shfl_xor(ut, off, 64);
+  }
+  const int total = base;
+  if (lane == 0) pre[nb] = total;
+  __syncthreads();
+  if (total > cap) {
+    if (I == 0 && lane == 0) atomicOr(&ctr->overflow, 1);
+    return;
+  }
+  if (I == 0) {
+    // flagged blocks of the iterate (statistics)
+    int nz = 0;
+    for (int r = lane; r < nb; r += 64) nz += sym.nzrow[r];
+    for (int off = 32; off > 0; off >>= 1) nz += __shfl_xor(nz, off, 64);
+    if (lane == 0) {
+      ctr->nnzb = total;
+      ctr->nupper = ut;
+      ctr->stored[iter] = total;
+      ctr->nonzero[iter] = nz;
+      Q.row_ptr[nb] = total;
     }
-    int o = base + incl - c;
+  }
+  const int row0 = pre[I];
+  if (lane == 0) Q.row_ptr[I] = row0;
+  int count;
+  {
+    const int c = __popc(bits);
+    int ic = c;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int x = __shfl_up(ic, off, 64);
+      if (lane >= off) ic += x;
+    }
+    int o = ic - c;
     uint32_t b = bits;
     while (b) {
       const int bit = __ffs(b) - 1;
       b &= b - 1;
-      const int J = 32 * w + bit;
+      const int J = 32 * lane + bit;
       cols[o] = J;
       Q.col[row0 + o] = J;
       Q.brow[row0 + o] = I;
       ++o;
     }
-    base += __shfl(incl, 63, 64);
+    count = __shfl(ic, 63, 64);
   }
   __syncthreads();
-  const int count = base;
-  const int wi = I >> 5;
   const uint32_t low = (1u << (I & 31)) - 1u;
   // columns before the diagonal block, which is always present
-  const int first = sym.wpre[static_cast<size_t>(I) * nbw + wi] +
-                    __popc(brow_bits[wi] & low);
-  const int u0 = sym.uptr[I];
+  const int first = wpre_i + __popc(static_cast<uint32_t>(__shfl(static_cast<int>(bits), wi, 64)) & low);
+  const int u0 = ub;
   for (int t = first + lane; t < count; t += 64) {
     const int J = cols[t];
     const int q = row0 + t;
@@ -268,8 +296,7 @@ __global__ __launch_bounds__(64) void bsr_symbolic_fill_kernel(
         atomicOr(&ctr->overflow, 2);
         continue;
       }
-      qT = Q.row_ptr[J] + sym.wpre[static_cast<size_t>(J) * nbw + wi] +
-           __popc(wj & low);
+      qT = pre[J] + sym.wpre[static_cast<size_t>(J) * nbw + wi] + __popc(wj & low);
     }
     BsrWork wk;
     wk.q = q;
@@ -754,12 +781,8 @@ hipError_t launch_bsr_symbolic(const BsrMat& A, int nb,
                      0, s, A, nb, nbw, sym, ctr, st, iter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bsr_symbolic_scan_kernel, dim3(1), dim3(kScanThreads), 0,
-                     s, sym, nb, Q.row_ptr, cap, ctr, st, iter);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bsr_symbolic_fill_kernel, dim3(nb), dim3(64), 0, s, sym,
-                     nb, nbw, Q, ctr, st);
+                     nb, nbw, Q, cap, ctr, st, iter);
   return hipGetLastError();
 }
 

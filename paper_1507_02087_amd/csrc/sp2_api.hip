@@ -1291,7 +1291,6 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   const size_t o_wp = take(static_cast<size_t>(nb) * nbw * sizeof(int32_t));
   const size_t o_qc = take(nb * sizeof(int32_t));
   const size_t o_uc = take(nb * sizeof(int32_t));
-  const size_t o_up = take((nb + 1) * sizeof(int32_t));
   const size_t o_nz = take(nb * sizeof(int32_t));
   const size_t o_pw = take(static_cast<size_t>(sp2::kMaxIter + 2) * grid * sizeof(uint32_t));
   const size_t o_wk = take(static_cast<size_t>(cap) * sizeof(sp2::BsrWork));
@@ -1319,7 +1318,6 @@ sp2_status sp2_init_bsr(sp2_ctx c, int64_t n, int32_t block, int64_t nnzb,
   c->b.sym.wpre = reinterpret_cast<int32_t*>(base + o_wp);
   c->b.sym.qcnt = reinterpret_cast<int32_t*>(base + o_qc);
   c->b.sym.ucnt = reinterpret_cast<int32_t*>(base + o_uc);
-  c->b.sym.uptr = reinterpret_cast<int32_t*>(base + o_up);
   c->b.sym.nzrow = reinterpret_cast<int32_t*>(base + o_nz);
   c->b.sym.prod_wg = reinterpret_cast<uint32_t*>(base + o_pw);
   c->b.sym.work = reinterpret_cast<sp2::BsrWork*>(base + o_wk);

@@ -423,7 +423,6 @@ struct BsrSymbolic {
   int32_t* wpre;      // nb x nbw
   int32_t* qcnt;      // nb
   int32_t* ucnt;      // nb
-  int32_t* uptr;      // nb + 1
   int32_t* nzrow;     // nb: flagged blocks per row of the iterate
   BsrWork* work;      // capacity
   // block products of each numeric workgroup per step ((kMaxIter + 2) x

@@ -150,3 +150,31 @@ def test_long_rows_and_ragged_tail():
     for k, (a, r) in enumerate(zip(hist["v"], ref.v)):
         if r > 1e-2:
             assert abs(a - r) <= 1e-4 * r, (k, a, r)
+
+
+def test_fill_beyond_capacity_reported():
+    """A block-tridiagonal F without truncation fills in (the pattern of X^2
+    has twice the block bandwidth of X's) until a pattern needs more blocks
+    than the library keeps room for (min(nb^2, 16 nnzb + 64 nb) = 28640 for
+    nb = 256): the fill kernel finds the total over capacity before writing
+    anything and the run stops with SP2_OUT_OF_MEMORY."""
+    import scipy.sparse as sps
+    import paper_1507_02087_amd as sp2
+    nb = 256
+    n = 32 * nb
+    rng = np.random.default_rng(256)
+    offs = list(range(0, 33))
+    B = sps.diags([rng.standard_normal(n - k) for k in offs], offs, shape=(n, n),
+                  format="csr")
+    F = (B + B.T).tocsr()
+    R = float(np.max(np.asarray(abs(F).sum(axis=1)).ravel()))
+    rp, ci, bl = to_bsr_blocks(F, 32)
+    assert rp[-1] == 3 * nb - 2          # block tridiagonal
+    print_case(f"bsr n={n} block-tridiagonal, tau=0, capacity overflow")
+    ctx = sp2.BsrContext(0)
+    ctx.init_bsr(n, *_dev(rp, ci, bl), -R, R, n // 2, trunc_tau=0.0)
+    with pytest.raises(sp2.SP2Error) as e:
+        ctx.run()
+    assert e.value.status == sp2.OUT_OF_MEMORY
+    assert "capacity" in str(e.value)
+    ctx.close()
