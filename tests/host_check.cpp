@@ -2,7 +2,8 @@
 // undefined-behaviour sanitizers by tests/test_host_sanitize.py (no GPU):
 // the launch planning (tile order, K-split tail tiles, per-XCD dealing) on
 // random groups, checked for exact coverage of every tile and K slice, and
-// the SP2-ACC schedule (Alg. 3) on random, edge and invalid bounds.
+// the SP2-ACC schedule (Alg. 3) on random, edge and invalid bounds, and the
+// storage order of the block-sparse blocks.
 // Prints "ok" and returns 0 when every check holds.
 #include <math.h>
 #include <stdio.h>
@@ -119,6 +120,37 @@ void check_plan_once(std::mt19937& rng) {
     CHECK(piece_seen[q] == 1, "piece %zu seen %d", q, piece_seen[q]);
 }
 
+// Block storage order of the block-sparse iterates (blk_off): a permutation
+// of the 1024 elements in which lane l = m + 32 g reads its MFMA operand
+// (row m, columns 16 g .. 16 g + 15) as four 16-byte loads at 256 u + 4 l,
+// and in which the four elements (r, 8 a + 4 h + e), e = 0..3, of a row are
+// consecutive (the stored transpose read for the old block, and the
+// transposed output block written as 16-byte stores).
+void check_blk_off() {
+  std::vector<int> seen(1024, 0);
+  for (int m = 0; m < 32; ++m)
+    for (int c = 0; c < 32; ++c) {
+      const int o = sp2::blk_off(m, c);
+      CHECK(o >= 0 && o < 1024, "blk_off(%d, %d) = %d", m, c, o);
+      if (o >= 0 && o < 1024) ++seen[o];
+    }
+  for (int o = 0; o < 1024; ++o) CHECK(seen[o] == 1, "offset %d used %d times", o, seen[o]);
+  for (int l = 0; l < 64; ++l)
+    for (int u = 0; u < 4; ++u)
+      for (int e = 0; e < 4; ++e) {
+        const int m = l & 31, g = l >> 5;
+        CHECK(sp2::blk_off(m, 16 * g + 4 * u + e) == 256 * u + 4 * l + e,
+              "operand load of lane %d, panel %d", l, u);
+      }
+  for (int r = 0; r < 32; ++r)
+    for (int h = 0; h < 2; ++h)
+      for (int a = 0; a < 4; ++a)
+        for (int e = 0; e < 4; ++e)
+          CHECK(sp2::blk_off(r, 8 * a + 4 * h + e) ==
+                    ((2 * a + h) & 3) * 256 + (r + 32 * (a >> 1)) * 4 + e,
+                "row segment (%d, %d, %d)", r, h, a);
+}
+
 void check_schedule(std::mt19937& rng) {
   std::uniform_real_distribution<double> u(0.0, 1.0);
   std::vector<int8_t> p(SP2_MAX_ITER_LIMIT);
@@ -174,6 +206,7 @@ int main() {
   std::mt19937 rng(20150708);
   check_row_stride();
   check_tile_list();
+  check_blk_off();
   for (int i = 0; i < 3000; ++i) check_plan_once(rng);
   check_schedule(rng);
   if (g_fail) {
